@@ -1,0 +1,330 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties an oracle function to a fact fixed by the paper or by plain
+mathematics: the brute-force four-index tensor of Eq. eq:df:eri, closed
+forms of special B, invariants of the Coulomb/exchange contractions, the
+packed order of numpy.tril_indices, and brute-force nearest-value search for
+the reduced formats.  Unpacking in these tests is done with
+numpy.tril_indices, not with the oracle's own index function.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def unpack_np(B, nao):
+    """Full B_P from packed rows using numpy.tril_indices (row, col), row >= col."""
+    r, c = np.tril_indices(nao)
+    Bf = np.zeros((B.shape[0], nao, nao))
+    Bf[:, r, c] = B[:, : r.size]
+    Bf[:, c, r] = B[:, : r.size]
+    return Bf
+
+
+def pack_np(Bf):
+    nao = Bf.shape[-1]
+    r, c = np.tril_indices(nao)
+    return np.ascontiguousarray(Bf[:, r, c])
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = synth.C1
+    R = synth.positions(cfg)
+    B = synth.B_full(cfg.seed, R, cfg.naux)
+    C = synth.C_occ(cfg.seed, cfg.nao, cfg.nocc)
+    return cfg, B, C, 2.0 * C @ C.T
+
+
+def test_pair_index_is_tril_order():
+    nao = 37
+    r, c = np.tril_indices(nao)
+    assert np.array_equal(synth.pair_index(r, c), np.arange(r.size))
+    assert np.array_equal(synth.pair_index(c, r), np.arange(r.size))
+
+
+def test_oracle_unpack_matches_tril(c1):
+    cfg, B, _, _ = c1
+    Bf = unpack_np(B[:3], cfg.nao)
+    for P in range(3):
+        assert np.array_equal(oracle.unpack(B[P], cfg.nao), Bf[P])
+
+
+def test_bruteforce_four_index(c1):
+    """Eq. eq:df:eri: (mu nu|ka la) = sum_P B B; J and K from the explicit
+    four-index tensor equal the oracle's factored contractions."""
+    cfg, B, C, D = c1
+    nao = cfg.nao
+    Bf = unpack_np(B, nao)
+    Bm = Bf.reshape(cfg.naux, nao * nao)
+    eri = (Bm.T @ Bm).reshape(nao, nao, nao, nao)  # (mu nu|ka la)
+    J_bf = np.einsum("mnkl,kl->mn", eri, D)
+    K_bf = np.einsum("mknl,kl->mn", eri, D)
+    assert rel(oracle.J(B, nao, D), J_bf) < 1e-13
+    assert rel(oracle.K_C(B, nao, C), K_bf) < 1e-13
+    assert rel(oracle.K_D(B, nao, D), K_bf) < 1e-13
+    # non-symmetric D: the K definition uses (mu ka|nu la) D[ka,la]
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((nao, nao))
+    assert rel(oracle.K_D(B, nao, A), np.einsum("mknl,kl->mn", eri, A)) < 1e-13
+    assert rel(oracle.J(B, nao, A), np.einsum("mnkl,kl->mn", eri, A)) < 1e-13
+
+
+def test_closed_form_rank_one():
+    """naux = 1, B_1 = u u^T: J = K = (u^T D u) u u^T."""
+    rng = np.random.default_rng(1)
+    nao, nocc = 9, 3
+    u = rng.standard_normal(nao)
+    B = pack_np(np.outer(u, u)[None])
+    C, _ = np.linalg.qr(rng.standard_normal((nao, nocc)))
+    D = 2 * C @ C.T
+    ref = (u @ D @ u) * np.outer(u, u)
+    assert rel(oracle.J(B, nao, D), ref) < 1e-14
+    assert rel(oracle.K_C(B, nao, C), ref) < 1e-14
+    assert rel(oracle.K_D(B, nao, D), ref) < 1e-14
+
+
+def test_closed_form_diagonal():
+    """B_P = diag(b_P): J = diag(sum_P b_P (b_P . diag D)); K = (b b^T) * D
+    summed over P (elementwise product)."""
+    rng = np.random.default_rng(2)
+    nao, naux, nocc = 11, 5, 4
+    b = rng.standard_normal((naux, nao))
+    Bf = np.zeros((naux, nao, nao))
+    for P in range(naux):
+        Bf[P] = np.diag(b[P])
+    B = pack_np(Bf)
+    C, _ = np.linalg.qr(rng.standard_normal((nao, nocc)))
+    D = 2 * C @ C.T
+    J_ref = np.diag(sum(b[P] * (b[P] @ np.diag(D)) for P in range(naux)))
+    K_ref = sum(np.outer(b[P], b[P]) * D for P in range(naux))
+    assert rel(oracle.J(B, nao, D), J_ref) < 1e-14
+    assert rel(oracle.K_C(B, nao, C), K_ref) < 1e-14
+    assert rel(oracle.K_D(B, nao, D), K_ref) < 1e-14
+
+
+def test_zero_density(c1):
+    cfg, B, _, _ = c1
+    Z = np.zeros((cfg.nao, cfg.nao))
+    assert np.all(oracle.J(B, cfg.nao, Z) == 0)
+    assert np.all(oracle.K_D(B, cfg.nao, Z) == 0)
+    assert np.all(oracle.K_C(B, cfg.nao, np.zeros((cfg.nao, 2))) == 0)
+
+
+def test_invariants(c1):
+    cfg, B, C, D = c1
+    nao = cfg.nao
+    Jm, r = oracle.J(B, nao, D, return_rho=True)
+    Km = oracle.K_C(B, nao, C)
+    # symmetry
+    assert np.max(np.abs(Jm - Jm.T)) < 1e-12 * np.abs(Jm).max()
+    assert np.max(np.abs(Km - Km.T)) < 1e-12 * np.abs(Km).max()
+    # E_J = 1/2 sum rho^2 = 1/2 tr(DJ)
+    EJ, EK = oracle.energies(r, D, Km)
+    assert abs(EJ - 0.5 * np.sum(D * Jm)) < 1e-12 * abs(EJ)
+    # tr(DK) >= 0 for PSD D, hence E_K <= 0
+    assert np.sum(D * Km) > 0 and EK < 0
+    # K from D equals K from C when D = 2 C C^T
+    assert rel(oracle.K_D(B, nao, D), Km) < 1e-13
+    # linearity in D
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((nao, nao))
+    A = A + A.T
+    assert rel(oracle.J(B, nao, D + 2.5 * A), Jm + 2.5 * oracle.J(B, nao, A)) < 1e-13
+    assert rel(oracle.K_D(B, nao, D + 2.5 * A), Km + 2.5 * oracle.K_D(B, nao, A)) < 1e-13
+    # B -> s B scales J, K by s^2
+    s = 1.75
+    assert rel(oracle.J(s * B, nao, D), s * s * Jm) < 1e-14
+    assert rel(oracle.K_C(s * B, nao, C), s * s * Km) < 1e-14
+
+
+def test_permutation_covariance(c1):
+    """Relabelling the AOs by a permutation pi maps J -> J[pi][:, pi]."""
+    cfg, B, C, D = c1
+    nao = cfg.nao
+    pi = np.random.default_rng(4).permutation(nao)
+    Bp = pack_np(unpack_np(B, nao)[:, pi][:, :, pi])
+    Cp = C[pi]
+    Dp = D[np.ix_(pi, pi)]
+    assert rel(oracle.J(Bp, nao, Dp), oracle.J(B, nao, D)[np.ix_(pi, pi)]) < 1e-13
+    assert rel(oracle.K_C(Bp, nao, Cp), oracle.K_C(B, nao, C)[np.ix_(pi, pi)]) < 1e-13
+
+
+def test_row_blocks_accumulate(c1):
+    """Streaming B in row blocks gives the same J and K."""
+    cfg, B, C, D = c1
+    nao = cfg.nao
+    r = oracle.rho(B, nao, D)
+    Jb = np.zeros((nao, nao))
+    Kb = np.zeros((nao, nao))
+    for P0 in range(0, cfg.naux, 100):
+        blk = B[P0:P0 + 100]
+        oracle.J_acc(blk, nao, r[P0:P0 + 100], Jb)
+        oracle.K_C_acc(blk, nao, C, Kb)
+    assert rel(Jb, oracle.J(B, nao, D)) < 1e-14
+    assert rel(Kb, oracle.K_C(B, nao, C)) < 1e-14
+
+
+def test_single_entries(c1):
+    cfg, B, C, _ = c1
+    nao = cfg.nao
+    Km = oracle.K_C(B, nao, C)
+    R = synth.positions(cfg)
+    for mu, nu in [(0, 0), (5, 63), (63, 63), (17, 40)]:
+        Bmu = synth.B_cols(cfg.seed, R, cfg.naux, synth.pair_index(mu, np.arange(nao)))
+        Bnu = synth.B_cols(cfg.seed, R, cfg.naux, synth.pair_index(nu, np.arange(nao)))
+        assert abs(oracle.K_C_entry(Bmu, Bnu, C) - Km[mu, nu]) < 1e-12 * np.abs(Km).max()
+
+
+# ----------------------------------------------------------- reduced formats
+def _all_finite(bits_to_f64):
+    vals = bits_to_f64(np.arange(65536, dtype=np.uint32))
+    vals = vals[np.isfinite(vals)]
+    return np.unique(vals)
+
+
+def _nearest_even(x, grid, bits_of):
+    """Brute-force RNE: nearest grid value, ties to the even bit pattern."""
+    i = np.searchsorted(grid, x)
+    out = np.empty_like(x)
+    for k, (xi, ii) in enumerate(zip(x, i)):
+        lo = grid[max(ii - 1, 0)]
+        hi = grid[min(ii, grid.size - 1)]
+        dl, dh = abs(xi - lo), abs(hi - xi)
+        if dl < dh:
+            out[k] = lo
+        elif dh < dl:
+            out[k] = hi
+        else:
+            out[k] = lo if int(bits_of(lo)) % 2 == 0 else hi
+    return out
+
+
+def _bf16_from_bits(b):
+    return (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _f16_from_bits(b):
+    return b.astype(np.uint16).view(np.float16).astype(np.float64)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f16"])
+def test_quantize_bruteforce(fmt):
+    if fmt == "bf16":
+        grid = _all_finite(_bf16_from_bits)
+        q = oracle.quantize_bf16
+        bits = lambda v: oracle.bf16_bits(np.array([v]))[0]  # noqa: E731
+        top = grid.max()
+    else:
+        grid = _all_finite(_f16_from_bits)
+        q = oracle.quantize_f16
+        bits = lambda v: oracle.f16_bits(np.array([v]))[0]  # noqa: E731
+        top = grid.max()
+    rng = np.random.default_rng(5)
+    mags = np.exp(rng.uniform(np.log(1e-9), np.log(top * 0.999), 4000))
+    x = mags * rng.choice([-1.0, 1.0], mags.size)
+    # exact midpoints between neighbours exercise ties
+    mids = 0.5 * (grid[1000:1100] + grid[1001:1101])
+    x = np.concatenate([x, mids, -mids])
+    assert np.array_equal(q(x), _nearest_even(x, grid, bits))
+
+
+def test_quantize_special_values():
+    q16, qb = oracle.quantize_f16, oracle.quantize_bf16
+    assert q16(np.array([65504.0]))[0] == 65504.0
+    assert np.isinf(q16(np.array([65520.0]))[0])          # halfway to 2^16 rounds to inf
+    assert q16(np.array([65519.99]))[0] == 65504.0
+    assert q16(np.array([2.0 ** -25]))[0] == 0.0          # tie with 0 -> even (0)
+    assert q16(np.array([3 * 2.0 ** -26]))[0] == 2.0 ** -24
+    assert qb(np.array([1 + 2.0 ** -8]))[0] == 1.0        # tie -> even
+    assert qb(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6
+    assert qb(np.array([1e-160]))[0] == 0.0
+    # single rounding from FP64 differs from rounding through FP32 here:
+    x = np.array([1 + 2.0 ** -8 + 2.0 ** -40])            # just above a bf16 tie
+    assert qb(x)[0] == 1 + 2.0 ** -7
+    assert np.float32(x[0]) == np.float32(1 + 2.0 ** -8)  # FP32 first would land on the tie
+    # numpy's direct double -> half conversion agrees
+    y = np.random.default_rng(6).standard_normal(20000) * 100
+    assert np.array_equal(q16(y), y.astype(np.float16).astype(np.float64))
+
+
+# ----------------------------------------------------------- SCF
+def test_scf_no_two_electron():
+    """B = 0: F = H, so E = 2 sum of the nocc lowest eigenvalues of H, and the
+    second iteration repeats the first."""
+    R = synth.positions_c5(7)
+    H = synth.core_hamiltonian(7, R)
+    nocc = 24
+    B = np.zeros((4, synth.npair(128)))
+    res = oracle.scf(B, H, nocc)
+    eps = np.linalg.eigvalsh(H)
+    assert abs(res["E"][0] - 2 * eps[:nocc].sum()) < 1e-12
+    assert res["converged"] and res["iterations"] == 2
+
+
+def test_diis_coefficients_sum_to_one():
+    rng = np.random.default_rng(8)
+    Fs = [rng.standard_normal((6, 6)) for _ in range(5)]
+    es = [rng.standard_normal((6, 6)) for _ in range(5)]
+    _, c = oracle.diis_extrapolate(Fs, es)
+    assert abs(c.sum() - 1) < 1e-12
+    # c minimises |sum c_i e_i| on the affine set: compare against the
+    # least-squares solution after eliminating the constraint
+    E = np.stack([e.ravel() for e in es], 1)
+    A = E[:, :-1] - E[:, -1:]
+    y, *_ = np.linalg.lstsq(A, -E[:, -1], rcond=None)
+    c_ls = np.append(y, 1 - y.sum())
+    assert np.allclose(c, c_ls, atol=1e-10)
+
+
+@pytest.mark.slow
+def test_scf_converged_state():
+    """At convergence: FD - DF ~ 0, D^2 = 2D, tr D = 2 nocc, and D is built
+    from the lowest nocc eigenvectors of its own Fock matrix (aufbau)."""
+    cfg = synth.C5
+    seed = 1
+    R = synth.positions_c5(seed)
+    B = synth.B_full(seed, R, cfg.naux) * synth.C5_B_SCALE
+    H = synth.core_hamiltonian(seed, R)
+    res = oracle.scf(B, H, cfg.nocc, conv_tol=1e-11, conv_tol_grad=1e-8)
+    assert res["converged"]
+    D = res["D"]
+    Jm = oracle.J(B, cfg.nao, D)
+    Km = oracle.K_D(B, cfg.nao, D)
+    F = H + Jm - 0.5 * Km
+    assert np.linalg.norm(F @ D - D @ F) < 1e-7
+    assert np.linalg.norm(D @ D - 2 * D) < 1e-10
+    assert abs(np.trace(D) - 2 * cfg.nocc) < 1e-10
+    eps, U = np.linalg.eigh(F)
+    Cl = U[:, : cfg.nocc]
+    assert np.linalg.norm(2 * Cl @ Cl.T - D) < 1e-6
+    assert eps[cfg.nocc] - eps[cfg.nocc - 1] > 0
+
+
+# ----------------------------------------------------------- MLP
+def test_mlp_gradient_finite_difference():
+    rng = np.random.default_rng(9)
+    sizes = [(7, 8), (7,), (5, 7), (5,), (1, 5), (1,)]
+    params = [rng.standard_normal(s) * 0.5 for s in sizes]
+    X = rng.standard_normal((13, 8))
+    t = rng.standard_normal(13)
+    L, grads = oracle.mlp_loss_grad(params, X, t)
+    h = 1e-6
+    for k, p in enumerate(params):
+        flat = p.ravel()
+        for j in range(0, flat.size, max(1, flat.size // 6)):
+            old = flat[j]
+            flat[j] = old + h
+            Lp, _ = oracle.mlp_loss_grad(params, X, t)
+            flat[j] = old - h
+            Lm, _ = oracle.mlp_loss_grad(params, X, t)
+            flat[j] = old
+            fd = (Lp - Lm) / (2 * h)
+            g = grads[k].ravel()[j]
+            assert abs(fd - g) <= 1e-7 * max(1.0, abs(g)), (k, j, fd, g)
