@@ -7,7 +7,7 @@ the only thing both sides use is the input generator in ``synth``.
 
 Contents, each following the passage it cites:
 
-* ``rho``, ``J``, ``K_C``, ``K_D``, ``K_C_entries`` -- the J/K contractions of
+* ``rho``, ``J``, ``K_C``, ``K_D``, ``K_C_rows`` -- the J/K contractions of
   Sec. IV.C.2, Eq. eq:df:eri, written as plain loops in ``oracle.c``.
 * ``energies`` -- E_J = 1/2 sum_P rho_P^2 = 1/2 tr(DJ) and E_K = -1/4 tr(DK).
 * ``scf`` -- restricted closed-shell SCF with Pulay DIIS (the default
@@ -55,7 +55,8 @@ def lib():
         L.oracle_K_D_acc.argtypes = [dp, i64, i64, i64, dp, dp]
         L.oracle_K_D_acc.restype = ctypes.c_int
         L.oracle_unpack.argtypes = [dp, i64, dp]
-        L.oracle_K_C_entry.argtypes = [dp, dp, i64, i64, dp, i64, dp]
+        L.oracle_K_C_rows.argtypes = [dp, i64, i64, i64, dp, i64, dp]
+        L.oracle_K_C_rows.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -134,16 +135,16 @@ def unpack(Brow: np.ndarray, nao: int) -> np.ndarray:
     return out
 
 
-def K_C_entry(Bmu: np.ndarray, Bnu: np.ndarray, C: np.ndarray) -> float:
-    """One exchange entry K[mu,nu] for D = 2CC^T from the row slices
-    Bmu[P, ka] = B_P[mu, ka] and Bnu[P, ka] = B_P[nu, ka]."""
-    Bmu = _f64(Bmu)
-    Bnu = _f64(Bnu)
+def K_C_rows(Bsel: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Exchange entries among a set of rows mu_r for D = 2CC^T, from the row
+    slices Bsel[r, P, ka] = B_P[mu_r, ka]: returns Ksel[r, s] = K[mu_r, mu_s]."""
+    Bsel = _f64(Bsel)
     C = _f64(C)
-    out = np.zeros(1)
-    lib().oracle_K_C_entry(_dp(Bmu), _dp(Bnu), C.shape[0], Bmu.shape[0], _dp(C), C.shape[1],
-                           _dp(out))
-    return float(out[0])
+    nsel, naux, nao = Bsel.shape
+    out = np.zeros((nsel, nsel))
+    if lib().oracle_K_C_rows(_dp(Bsel), nsel, nao, naux, _dp(C), C.shape[1], _dp(out)) != 0:
+        raise MemoryError("oracle_K_C_rows")
+    return out
 
 
 def energies(rho_: np.ndarray, D: np.ndarray, K: np.ndarray):

@@ -47,29 +47,63 @@ int oracle_num_threads(void) {
 #endif
 }
 
-/* rho_P = sum_{ka,la} B_P[ka,la] D[ka,la] for each of the nrows rows. */
+/*
+ * rho_P = sum_{ka,la} B_P[ka,la] D[ka,la] for each of the nrows rows.
+ * B_P is symmetric, so the double sum is taken over the packed pairs
+ * ka <= la of row P in storage order, each off-diagonal pair carrying both
+ * D[ka,la] and D[la,ka]: the same terms, grouped by pair (exact for any D).
+ */
 void oracle_rho(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* D,
                 double* rho) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t P = 0; P < nrows; ++P) {
         const double* Brow = B + P * ldB;
         double s = 0.0;
-        for (int64_t ka = 0; ka < nao; ++ka)
-            for (int64_t la = 0; la < nao; ++la) s += bval(Brow, ka, la) * D[ka * nao + la];
+        for (int64_t la = 0; la < nao; ++la)
+            for (int64_t ka = 0; ka <= la; ++ka) {
+                const double b = Brow[pidx(ka, la)];
+                if (ka == la)
+                    s += b * D[la * nao + la];
+                else
+                    s += b * D[ka * nao + la] + b * D[la * nao + ka];
+            }
         rho[P] = s;
     }
 }
 
-/* J[mu,nu] += sum_P rho_P B_P[mu,nu] over the nrows rows given. */
+/*
+ * J[mu,nu] += sum_P rho_P B_P[mu,nu] over the nrows rows given.  The sum over
+ * P is formed per packed pair (rows of B in order), then written to both
+ * (mu,nu) and (nu,mu).
+ */
 void oracle_J_acc(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* rho,
                   double* J) {
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t mu = 0; mu < nao; ++mu)
-        for (int64_t nu = 0; nu < nao; ++nu) {
-            double s = 0.0;
-            for (int64_t P = 0; P < nrows; ++P) s += rho[P] * bval(B + P * ldB, mu, nu);
-            J[mu * nao + nu] += s;
+    const int64_t npair = nao * (nao + 1) / 2;
+#pragma omp parallel
+    {
+        const int64_t blk = 4096;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t p0 = 0; p0 < npair; p0 += blk) {
+            const int64_t p1 = p0 + blk < npair ? p0 + blk : npair;
+            double acc[4096];
+            for (int64_t p = p0; p < p1; ++p) acc[p - p0] = 0.0;
+            for (int64_t P = 0; P < nrows; ++P) {
+                const double* Brow = B + P * ldB;
+                for (int64_t p = p0; p < p1; ++p) acc[p - p0] += rho[P] * Brow[p];
+            }
+            /* write each pair of this block to both triangles */
+            for (int64_t nu = 0; nu < nao; ++nu) {
+                const int64_t base = nu * (nu + 1) / 2;
+                if (base + nu < p0 || base >= p1) continue;
+                for (int64_t mu = 0; mu <= nu; ++mu) {
+                    const int64_t p = base + mu;
+                    if (p < p0 || p >= p1) continue;
+                    J[mu * nao + nu] += acc[p - p0];
+                    if (mu != nu) J[nu * nao + mu] += acc[p - p0];
+                }
+            }
         }
+    }
 }
 
 /* Unpack one packed row into a full symmetric nao x nao matrix. */
@@ -181,27 +215,34 @@ int oracle_K_D_acc(const double* B, int64_t ldB, int64_t nao, int64_t nrows, con
 }
 
 /*
- * Single exchange entries for D = 2 C C^T from the B rows that hold them:
- * out[s] = 2 sum_P sum_i (sum_ka B_P[mu_s,ka] C[ka,i]) (sum_la B_P[nu_s,la] C[la,i]).
- * Brow_mu[s] points at a (naux x nao) array holding B_P[mu_s, ka] for all P
- * and ka (row-major), Brow_nu likewise for nu_s; they are the sampled columns
- * p(mu_s, ka) of B, so full-size checks need only those columns.
+ * Exchange entries among a set of rows, for D = 2 C C^T:
+ *   Ksel[r][s] = 2 sum_P sum_i X_P[mu_r,i] X_P[mu_s,i],
+ *   X_P[mu_r,i] = sum_ka B_P[mu_r,ka] C[ka,i].
+ * Bsel is nsel x naux x nao with Bsel[r][P][ka] = B_P[mu_r, ka] (the packed
+ * columns p(mu_r, ka) of B), so full-size checks need only those columns.
  */
-void oracle_K_C_entry(const double* Bmu, const double* Bnu, int64_t nao, int64_t naux,
-                      const double* C, int64_t nocc, double* out) {
-    double total = 0.0;
-#pragma omp parallel for reduction(+ : total) schedule(dynamic, 4)
-    for (int64_t P = 0; P < naux; ++P) {
-        double sP = 0.0;
-        for (int64_t i = 0; i < nocc; ++i) {
-            double xm = 0.0, xn = 0.0;
-            for (int64_t ka = 0; ka < nao; ++ka) {
-                xm += Bmu[P * nao + ka] * C[ka * nocc + i];
-                xn += Bnu[P * nao + ka] * C[ka * nocc + i];
+int oracle_K_C_rows(const double* Bsel, int64_t nsel, int64_t nao, int64_t naux, const double* C,
+                    int64_t nocc, double* Ksel) {
+    double* Xs = (double*)malloc((size_t)(nsel * naux * nocc) * sizeof(double));
+    if (!Xs) return -1;
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+    for (int64_t r = 0; r < nsel; ++r)
+        for (int64_t P = 0; P < naux; ++P)
+            for (int64_t i = 0; i < nocc; ++i) {
+                const double* b = Bsel + (r * naux + P) * nao;
+                double x = 0.0;
+                for (int64_t ka = 0; ka < nao; ++ka) x += b[ka] * C[ka * nocc + i];
+                Xs[(r * naux + P) * nocc + i] = x;
             }
-            sP += xm * xn;
+#pragma omp parallel for collapse(2)
+    for (int64_t r = 0; r < nsel; ++r)
+        for (int64_t q = 0; q < nsel; ++q) {
+            double s = 0.0;
+            for (int64_t P = 0; P < naux; ++P)
+                for (int64_t i = 0; i < nocc; ++i)
+                    s += Xs[(r * naux + P) * nocc + i] * Xs[(q * naux + P) * nocc + i];
+            Ksel[r * nsel + q] = 2.0 * s;
         }
-        total += 2.0 * sP;
-    }
-    *out = total;
+    free(Xs);
+    return 0;
 }

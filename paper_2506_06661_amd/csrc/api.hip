@@ -1,0 +1,293 @@
+// C-ABI entry points of libdfjk: argument checks, handle lifetime, dispatch.
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace dfjk {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+int DevBuf::ensure(size_t want) {
+    if (want <= bytes && ptr) return DFJK_OK;
+    release();
+    if (want == 0) want = 256;
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        ptr = nullptr;
+        bytes = 0;
+        set_error("device allocation of %zu bytes failed", want);
+        return DFJK_E_OOM;
+    }
+    bytes = want;
+    return DFJK_OK;
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+static int check_handle(const dfjk_ctx* h) {
+    if (!h) {
+        set_error("null handle");
+        return DFJK_E_INVALID;
+    }
+    return DFJK_OK;
+}
+
+}  // namespace dfjk
+
+using namespace dfjk;
+
+extern "C" {
+
+void dfjk_default_options(dfjk_options* o) {
+    if (!o) return;
+    o->diis_space = 8;
+    o->conv_tol = 1e-9;
+    o->conv_tol_grad = 3e-5;
+    o->max_cycle = 100;
+    o->compensated_j = 1;
+}
+
+const char* dfjk_last_error(void) { return g_err; }
+
+int dfjk_init(dfjk_handle* out, const void* B_dev, int dtype, int64_t nao, int64_t naux, int64_t ldB,
+              void* stream, const dfjk_options* opts) {
+    clear_error();
+    if (!out) {
+        set_error("dfjk_init: null handle pointer");
+        return DFJK_E_INVALID;
+    }
+    *out = nullptr;
+    if (!B_dev) {
+        set_error("dfjk_init: null B");
+        return DFJK_E_INVALID;
+    }
+    if (dtype < DFJK_F64 || dtype > DFJK_F16) {
+        set_error("dfjk_init: unknown dtype %d", dtype);
+        return DFJK_E_INVALID;
+    }
+    if (nao < 1 || nao > 65535 || naux < 1 || naux > (int64_t(1) << 31)) {
+        set_error("dfjk_init: nao=%lld naux=%lld out of range", (long long)nao, (long long)naux);
+        return DFJK_E_INVALID;
+    }
+    const int64_t npair = nao * (nao + 1) / 2;
+    if (ldB < npair) {
+        set_error("dfjk_init: ldB=%lld < nao(nao+1)/2=%lld", (long long)ldB, (long long)npair);
+        return DFJK_E_INVALID;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error("dfjk_init: no HIP device available");
+        return DFJK_E_NO_DEVICE;
+    }
+    dfjk_ctx* h = new (std::nothrow) dfjk_ctx();
+    if (!h) {
+        set_error("dfjk_init: host allocation failed");
+        return DFJK_E_OOM;
+    }
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        set_error("dfjk_init: hipGetDevice failed");
+        return DFJK_E_HIP;
+    }
+    h->stream = (hipStream_t)stream;
+    h->B = B_dev;
+    h->dtype = dtype;
+    h->nao = nao;
+    h->naux = naux;
+    h->ldB = ldB;
+    h->npair = npair;
+    if (opts)
+        h->opts = *opts;
+    else
+        dfjk_default_options(&h->opts);
+    int rc = j_setup(h);
+    if (rc != DFJK_OK) {
+        dfjk_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return DFJK_OK;
+}
+
+int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!D_dev || !J_dev) {
+        set_error("dfjk_build_J: null D or J");
+        return DFJK_E_INVALID;
+    }
+    return j_build(h, D_dev, J_dev, rho_dev);
+}
+
+int dfjk_build_K_factored(dfjk_handle h, const double* C_dev, int64_t ncol, const double* sign_dev,
+                          double scale, double* K_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!C_dev || !K_dev) {
+        set_error("dfjk_build_K_factored: null C or K");
+        return DFJK_E_INVALID;
+    }
+    if (ncol < 1 || ncol > h->nao) {
+        set_error("dfjk_build_K_factored: ncol=%lld outside [1, nao=%lld]", (long long)ncol,
+                  (long long)h->nao);
+        return DFJK_E_INVALID;
+    }
+    return k_build_factored(h, C_dev, ncol, sign_dev, scale, K_dev);
+}
+
+int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const double* D_dev,
+                 double* K_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!K_dev) {
+        set_error("dfjk_build_K: null K");
+        return DFJK_E_INVALID;
+    }
+    if (Cocc_dev) {
+        if (nocc < 1 || nocc > h->nao) {
+            set_error("dfjk_build_K: nocc=%lld outside [1, nao=%lld]", (long long)nocc,
+                      (long long)h->nao);
+            return DFJK_E_INVALID;
+        }
+        return k_build_factored(h, Cocc_dev, nocc, nullptr, 2.0, K_dev);
+    }
+    if (!D_dev) {
+        set_error("dfjk_build_K: both Cocc and D are null");
+        return DFJK_E_INVALID;
+    }
+    return k_build_from_D(h, D_dev, K_dev);
+}
+
+int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!bytes) {
+        set_error("dfjk_workspace_bytes: null output");
+        return DFJK_E_INVALID;
+    }
+    *bytes = h->dt.bytes + h->rho_part.bytes + h->rho.bytes + h->jpart.bytes + h->X.bytes +
+             h->kpart.bytes + h->ones.bytes + h->Cw.bytes + h->eig.bytes;
+    return DFJK_OK;
+}
+
+static void prof_free(dfjk_ctx* h) {
+    for (int p = 0; p < PH_COUNT; ++p) {
+        if (h->prof.ev[p]) {
+            for (int i = 0; i < 2 * h->prof.cap; ++i) (void)hipEventDestroy(h->prof.ev[p][i]);
+            delete[] h->prof.ev[p];
+            h->prof.ev[p] = nullptr;
+        }
+        h->prof.n[p] = 0;
+    }
+    h->prof.cap = 0;
+    h->prof.on = false;
+}
+
+int dfjk_profile(dfjk_handle h, int capacity) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (capacity < 0 || capacity > 4096) {
+        set_error("dfjk_profile: capacity %d outside [0, 4096]", capacity);
+        return DFJK_E_INVALID;
+    }
+    DFJK_HIP_TRY(hipStreamSynchronize(h->stream));
+    prof_free(h);
+    if (capacity == 0) return DFJK_OK;
+    h->prof.cap = capacity;  // phases before a failing one hold all 2*cap events
+    for (int p = 0; p < PH_COUNT; ++p) {
+        h->prof.ev[p] = new (std::nothrow) hipEvent_t[2 * capacity];
+        if (!h->prof.ev[p]) {
+            prof_free(h);
+            set_error("dfjk_profile: host allocation failed");
+            return DFJK_E_OOM;
+        }
+        for (int i = 0; i < 2 * capacity; ++i) {
+            if (hipEventCreate(&h->prof.ev[p][i]) != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->prof.ev[p][j]);
+                delete[] h->prof.ev[p];
+                h->prof.ev[p] = nullptr;
+                prof_free(h);
+                set_error("dfjk_profile: hipEventCreate failed");
+                return DFJK_E_HIP;
+            }
+        }
+    }
+    h->prof.on = true;
+    return DFJK_OK;
+}
+
+int dfjk_profile_read(dfjk_handle h, double* total_ms, int* counts, int nphase) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!total_ms || !counts || nphase < 1) {
+        set_error("dfjk_profile_read: null output or nphase < 1");
+        return DFJK_E_INVALID;
+    }
+    DFJK_HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int p = 0; p < nphase; ++p) {
+        total_ms[p] = 0.0;
+        counts[p] = 0;
+        if (p >= PH_COUNT || !h->prof.on) continue;
+        for (int i = 0; i < h->prof.n[p]; ++i) {
+            float ms = 0.f;
+            DFJK_HIP_TRY(hipEventElapsedTime(&ms, h->prof.ev[p][2 * i], h->prof.ev[p][2 * i + 1]));
+            total_ms[p] += ms;
+        }
+        counts[p] = h->prof.n[p];
+        h->prof.n[p] = 0;
+    }
+    return DFJK_OK;
+}
+
+void dfjk_destroy(dfjk_handle h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    prof_free(h);
+    h->dt.release();
+    h->rho_part.release();
+    h->rho.release();
+    h->jpart.release();
+    h->X.release();
+    h->kpart.release();
+    h->ones.release();
+    h->Cw.release();
+    h->eig.release();
+    delete h;
+}
+
+int dfjk_quantize(const double* src_dev, void* dst_dev, int dtype, int64_t n, void* stream) {
+    clear_error();
+    if (!src_dev || !dst_dev || n < 0) {
+        set_error("dfjk_quantize: null pointer or negative n");
+        return DFJK_E_INVALID;
+    }
+    if (dtype < DFJK_F32 || dtype > DFJK_F16) {
+        set_error("dfjk_quantize: dtype %d is not a reduced format", dtype);
+        return DFJK_E_INVALID;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error("dfjk_quantize: no HIP device available");
+        return DFJK_E_NO_DEVICE;
+    }
+    return quantize(src_dev, dst_dev, dtype, n, (hipStream_t)stream);
+}
+
+}  // extern "C"

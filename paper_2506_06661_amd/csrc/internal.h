@@ -1,0 +1,106 @@
+// Internal declarations shared by the libdfjk translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/dfjk.h"
+
+namespace dfjk {
+
+// Thread-local error text behind dfjk_last_error().
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define DFJK_HIP_TRY(expr)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            ::dfjk::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                              __LINE__);                                                       \
+            return DFJK_E_HIP;                                                                 \
+        }                                                                                      \
+    } while (0)
+
+#define DFJK_LAUNCH_CHECK(what)                                                                   \
+    do {                                                                                          \
+        hipError_t e_ = hipGetLastError();                                                        \
+        if (e_ != hipSuccess) {                                                                   \
+            ::dfjk::set_error("launch of %s failed: %s", what, hipGetErrorString(e_));            \
+            return DFJK_E_HIP;                                                                    \
+        }                                                                                         \
+    } while (0)
+
+// Grow-only device buffer owned by a handle.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t want);  // returns DFJK_OK / DFJK_E_OOM
+    void release();
+};
+
+// Per-phase event timing (dfjk_profile): a ring of event pairs per phase,
+// recorded on the handle's stream around each kernel when enabled.
+enum ProfPhase { PH_J = 0, PH_J_RHO, PH_J_OUT, PH_K, PH_K_GEMM1, PH_K_SYRK, PH_K_FINISH, PH_COUNT };
+
+struct Prof {
+    bool on = false;
+    int cap = 0;
+    hipEvent_t* ev[PH_COUNT] = {};  // 2*cap events per phase
+    int n[PH_COUNT] = {};           // pairs recorded since the last read
+    void begin(int ph, hipStream_t s) {
+        if (on && n[ph] < cap) (void)hipEventRecord(ev[ph][2 * n[ph]], s);
+    }
+    void end(int ph, hipStream_t s) {
+        if (on && n[ph] < cap) (void)hipEventRecord(ev[ph][2 * n[ph] + 1], s), ++n[ph];
+    }
+};
+
+}  // namespace dfjk
+
+struct dfjk_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    const void* B = nullptr;
+    int dtype = DFJK_F64;
+    int64_t nao = 0, naux = 0, ldB = 0, npair = 0;
+    dfjk_options opts{};
+
+    // J workspace
+    dfjk::DevBuf dt;        // packed density, npair doubles (plus FP32 hi/lo for reduced B)
+    dfjk::DevBuf rho_part;  // naux x j_chunks partial sums
+    dfjk::DevBuf rho;       // naux
+    dfjk::DevBuf jpart;     // j_splits x npair partial sums
+    int j_chunks = 1, j_splits = 1;
+
+    // K workspace
+    dfjk::DevBuf X;         // (naux * ncol) x ldx, element type per path
+    dfjk::DevBuf kpart;     // split partial tiles
+    dfjk::DevBuf ones;      // default +1 signs
+    dfjk::DevBuf Cw;        // staged (converted) C
+    dfjk::DevBuf eig;       // eigen-work for the D path
+
+    dfjk::Prof prof;
+};
+
+namespace dfjk {
+
+// J launchers (j_kernels.hip)
+int j_setup(dfjk_ctx* h);
+int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out);
+int j_build_reduced(dfjk_ctx* h, const double* D, double* J, double* rho_out);
+
+// K launchers (k_kernels.hip)
+int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
+                     double* K);
+int k_build_from_D(dfjk_ctx* h, const double* D, double* K);
+
+// quantisation (quantize.hip)
+int quantize(const double* src, void* dst, int dtype, int64_t n, hipStream_t s);
+
+inline size_t dtype_size(int dt) { return dt == DFJK_F64 ? 8 : dt == DFJK_F32 ? 4 : 2; }
+
+}  // namespace dfjk

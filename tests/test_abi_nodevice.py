@@ -1,0 +1,62 @@
+"""The C-ABI library loads, exports every function include/dfjk.h declares,
+and rejects bad arguments before touching a device.  Runs without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dfjk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfjk_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2506_06661_amd as pkg
+    return pkg.lib()
+
+
+def test_exports_every_declared_function(L):
+    names = declared_functions()
+    assert "dfjk_init" in names and "dfjk_build_J" in names and "dfjk_build_K" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_invalid_arguments(L):
+    import paper_2506_06661_amd as pkg
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096)
+    assert L.dfjk_init(None, fake, 0, 4, 4, 10, None, None) == -1
+    assert L.dfjk_init(ctypes.byref(h), None, 0, 4, 4, 10, None, None) == -1
+    assert "null B" in pkg.dfjk_last_error()
+    assert L.dfjk_init(ctypes.byref(h), fake, 9, 4, 4, 10, None, None) == -1
+    assert L.dfjk_init(ctypes.byref(h), fake, 0, 0, 4, 10, None, None) == -1
+    assert L.dfjk_init(ctypes.byref(h), fake, 0, 4, 0, 10, None, None) == -1
+    assert L.dfjk_init(ctypes.byref(h), fake, 0, 4, 4, 9, None, None) == -1  # ldB < npair
+    assert "ldB" in pkg.dfjk_last_error()
+    assert L.dfjk_build_J(None, fake, fake, None) == -1
+    assert L.dfjk_build_K(None, fake, 3, None, fake) == -1
+    assert L.dfjk_build_K_factored(None, fake, 3, None, ctypes.c_double(1.0), fake) == -1
+    n = ctypes.c_size_t()
+    assert L.dfjk_workspace_bytes(None, ctypes.byref(n)) == -1
+    L.dfjk_destroy(None)  # no-op
+    assert L.dfjk_quantize(None, fake, 2, 10, None) == -1
+    assert L.dfjk_quantize(fake, fake, 0, 10, None) == -1  # F64 is not a reduced format
+
+
+def test_no_device_reported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_2506_06661_amd as pkg
+    L = pkg.lib()
+    h = ctypes.c_void_p()
+    assert L.dfjk_init(ctypes.byref(h), ctypes.c_void_p(4096), 0, 4, 4, 10, None, None) == -2
+    assert "no HIP device" in pkg.dfjk_last_error()

@@ -171,15 +171,16 @@ def test_row_blocks_accumulate(c1):
     assert rel(Kb, oracle.K_C(B, nao, C)) < 1e-14
 
 
-def test_single_entries(c1):
+def test_selected_rows(c1):
     cfg, B, C, _ = c1
     nao = cfg.nao
     Km = oracle.K_C(B, nao, C)
     R = synth.positions(cfg)
-    for mu, nu in [(0, 0), (5, 63), (63, 63), (17, 40)]:
-        Bmu = synth.B_cols(cfg.seed, R, cfg.naux, synth.pair_index(mu, np.arange(nao)))
-        Bnu = synth.B_cols(cfg.seed, R, cfg.naux, synth.pair_index(nu, np.arange(nao)))
-        assert abs(oracle.K_C_entry(Bmu, Bnu, C) - Km[mu, nu]) < 1e-12 * np.abs(Km).max()
+    rows = np.array([0, 5, 17, 40, 63])
+    Bsel = np.stack([synth.B_cols(cfg.seed, R, cfg.naux, synth.pair_index(mu, np.arange(nao)))
+                     for mu in rows])
+    Ksel = oracle.K_C_rows(Bsel, C)
+    assert np.abs(Ksel - Km[np.ix_(rows, rows)]).max() < 1e-12 * np.abs(Km).max()
 
 
 # ----------------------------------------------------------- reduced formats
