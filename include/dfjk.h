@@ -133,6 +133,19 @@ int dfjk_build_K_factored(dfjk_handle h, const double* C_dev, int64_t ncol,
 int dfjk_profile(dfjk_handle h, int capacity);
 int dfjk_profile_read(dfjk_handle h, double* total_ms, int* counts, int nphase);
 
+/*
+ * Tile shapes (for autotuning).  DFJK_TILE_GEMM1 selects the X = B_P C
+ * kernel's workgroup tile.  dfjk_tile_count returns the number of compiled
+ * tiles; dfjk_tile_info gives tile `index` as (p0, p1) = (row tiles of 16
+ * occupied orbitals, column tiles of 16 basis functions per wavefront);
+ * dfjk_set_tile makes the handle use tile `index` (-1 = built-in heuristic).
+ * Every tile computes the same X up to summation order.
+ */
+enum { DFJK_TILE_GEMM1 = 0 };
+int dfjk_tile_count(int kernel);
+int dfjk_tile_info(int kernel, int index, int* p0, int* p1);
+int dfjk_set_tile(dfjk_handle h, int kernel, int index);
+
 /* Device workspace currently held by the handle, in bytes. */
 int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes);
 

@@ -174,6 +174,39 @@ int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const doub
     return k_build_from_D(h, D_dev, K_dev);
 }
 
+int dfjk_tile_count(int kernel) {
+    clear_error();
+    if (kernel != DFJK_TILE_GEMM1) {
+        set_error("dfjk_tile_count: unknown kernel %d", kernel);
+        return DFJK_E_INVALID;
+    }
+    return k_tile_count();
+}
+
+int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
+    clear_error();
+    if (kernel != DFJK_TILE_GEMM1 || !p0 || !p1) {
+        set_error("dfjk_tile_info: unknown kernel or null output");
+        return DFJK_E_INVALID;
+    }
+    if (k_tile_info(index, p0, p1) != DFJK_OK) {
+        set_error("dfjk_tile_info: index %d out of range", index);
+        return DFJK_E_INVALID;
+    }
+    return DFJK_OK;
+}
+
+int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (kernel != DFJK_TILE_GEMM1 || index < -1 || index >= k_tile_count()) {
+        set_error("dfjk_set_tile: kernel %d / index %d invalid", kernel, index);
+        return DFJK_E_INVALID;
+    }
+    h->g1_tile = index;
+    return DFJK_OK;
+}
+
 int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes) {
     clear_error();
     if (int rc = check_handle(h)) return rc;

@@ -83,6 +83,8 @@ struct dfjk_ctx {
     dfjk::DevBuf Cw;        // staged (converted) C
     dfjk::DevBuf eig;       // eigen-work for the D path
 
+    int g1_tile = -1;       // GEMM1 tile index (-1: heuristic)
+
     dfjk::Prof prof;
 };
 
@@ -97,6 +99,8 @@ int j_build_reduced(dfjk_ctx* h, const double* D, double* J, double* rho_out);
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
                      double* K);
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K);
+int k_tile_count();
+int k_tile_info(int t, int* ni, int* wm);
 
 // quantisation (quantize.hip)
 int quantize(const double* src, void* dst, int dtype, int64_t n, hipStream_t s);

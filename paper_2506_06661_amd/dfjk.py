@@ -57,9 +57,12 @@ def lib():
         L.dfjk_default_options.argtypes = [ctypes.POINTER(Options)]
         L.dfjk_default_options.restype = None
         L.dfjk_quantize.argtypes = [vp, vp, i32, i64, vp]
+        L.dfjk_tile_count.argtypes = [i32]
+        L.dfjk_tile_info.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.dfjk_set_tile.argtypes = [vp, i32, i32]
         L.dfjk_profile.argtypes = [vp, i32]
         L.dfjk_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]
-        for name in ("dfjk_profile", "dfjk_profile_read", "dfjk_init", "dfjk_build_J", "dfjk_build_K", "dfjk_build_K_factored",
+        for name in ("dfjk_tile_count", "dfjk_tile_info", "dfjk_set_tile", "dfjk_profile", "dfjk_profile_read", "dfjk_init", "dfjk_build_J", "dfjk_build_K", "dfjk_build_K_factored",
                      "dfjk_workspace_bytes", "dfjk_quantize"):
             getattr(L, name).restype = i32
         _lib = L
@@ -124,6 +127,23 @@ def dfjk_workspace_bytes(h) -> int:
     n = ctypes.c_size_t()
     _check("dfjk_workspace_bytes", lib().dfjk_workspace_bytes(h, ctypes.byref(n)))
     return n.value
+
+
+DFJK_TILE_GEMM1 = 0
+
+
+def dfjk_tile_count(kernel: int = DFJK_TILE_GEMM1) -> int:
+    return _check("dfjk_tile_count", lib().dfjk_tile_count(kernel))
+
+
+def dfjk_tile_info(kernel: int, index: int):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check("dfjk_tile_info", lib().dfjk_tile_info(kernel, index, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def dfjk_set_tile(h, kernel: int, index: int) -> int:
+    return _check("dfjk_set_tile", lib().dfjk_set_tile(h, kernel, index))
 
 
 PHASES = ("J", "J_rho", "J_out", "K", "K_gemm1", "K_syrk", "K_finish")

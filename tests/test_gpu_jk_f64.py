@@ -93,3 +93,16 @@ def test_invalid_nocc(pkg):
         pkg.dfjk_build_K(h.h, dev(C), nao + 1, None, K)
     with pytest.raises(pkg.DFJKError):
         pkg.dfjk_build_K(h.h, dev(C), 0, None, K)
+
+
+def test_every_gemm1_tile(pkg):
+    """Each compiled GEMM1 tile gives the oracle's K (ragged nao, nocc)."""
+    nao, naux, nocc = 300, 21, 37
+    R, B, C = system(nao, naux, nocc, 25)
+    K_ref = oracle.K_C(B, nao, C)
+    h = pkg.Handle(dev(B), nao)
+    Cd = dev(C)
+    for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_GEMM1)):
+        pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_GEMM1, t)
+        K = host(h.K(C=Cd))
+        assert max_rel(K, K_ref) < TOL, (t, pkg.dfjk_tile_info(pkg.DFJK_TILE_GEMM1, t))
