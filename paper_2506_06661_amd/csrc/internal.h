@@ -93,7 +93,6 @@ namespace dfjk {
 // J launchers (j_kernels.hip)
 int j_setup(dfjk_ctx* h);
 int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out);
-int j_build_reduced(dfjk_ctx* h, const double* D, double* J, double* rho_out);
 
 // K launchers (k_kernels.hip)
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,

@@ -179,6 +179,227 @@ __global__ __launch_bounds__(kThreads) void j_finish(const double* __restrict__ 
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ---------------------------------------------------------------- reduced B
+// B in FP32, BF16 or FP16.  Every element converts exactly to FP32.  Three
+// accumulation modes (the `compensated_j` option):
+//   ACC_F64  products and sums in FP64 (the FP64 VALU runs at full rate on
+//            MI355X, so this costs about one instruction per element);
+//   ACC_DOT2 FP32 compensated dot product (Dot2: TwoProduct + TwoSum) with the
+//            FP64 multiplier split into FP32 hi + lo parts;
+//   ACC_F32  plain FP32 fused multiply-add with the hi part.
+enum { ACC_F32 = 0, ACC_DOT2 = 1, ACC_F64 = 2 };
+
+template <typename TB>
+struct Elem;
+template <>
+struct Elem<float> {
+    static constexpr int V = 4;  // elements per 16-byte load
+    __device__ static float f(float x) { return x; }
+};
+template <>
+struct Elem<uint16_t> {  // bfloat16 bit pattern
+    static constexpr int V = 8;
+    __device__ static float f(uint16_t x) { return __uint_as_float((uint32_t)x << 16); }
+};
+template <>
+struct Elem<_Float16> {
+    static constexpr int V = 8;
+    __device__ static float f(_Float16 x) { return (float)x; }
+};
+
+template <typename TB>
+__device__ inline void load16(const TB* p, float* out) {
+    constexpr int V = Elem<TB>::V;
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const u4 raw = __builtin_nontemporal_load(reinterpret_cast<const u4*>(p));
+    const TB* e = reinterpret_cast<const TB*>(&raw);
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = Elem<TB>::f(e[v]);
+}
+
+template <int ACC>
+struct Acc {
+    double d = 0.0;
+    float s = 0.f, c = 0.f;
+    __device__ inline void add(float b, double m, float mhi, float mlo) {
+        if (ACC == ACC_F64) {
+            d = fma((double)b, m, d);
+        } else if (ACC == ACC_F32) {
+            s = __builtin_fmaf(b, mhi, s);
+        } else {
+            dot2_step(b, mhi, s, c);
+            c = __builtin_fmaf(b, mlo, c);
+        }
+    }
+    __device__ inline double value() const {
+        if (ACC == ACC_F64) return d;
+        if (ACC == ACC_F32) return (double)s;
+        return (double)s + (double)c;
+    }
+};
+
+// dt_hi = fl32(dt), dt_lo = fl32(dt - dt_hi)
+__global__ void split_f64(const double* __restrict__ x, int64_t n, float* __restrict__ hi,
+                          float* __restrict__ lo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float h = (float)x[i];
+    hi[i] = h;
+    lo[i] = (float)(x[i] - (double)h);
+}
+
+template <typename TB, int R, int ACC>
+__global__ __launch_bounds__(kThreads) void j_rho_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
+                                                       int64_t npair, const double* __restrict__ dt,
+                                                       const float* __restrict__ dhi,
+                                                       const float* __restrict__ dlo, int64_t chunk,
+                                                       int nchunk, bool vec, double* __restrict__ part) {
+    constexpr int V = Elem<TB>::V;
+    __shared__ double lds[4];
+    const int64_t P0 = (int64_t)blockIdx.x * R;
+    const int c = blockIdx.y;
+    const int64_t c0 = (int64_t)c * chunk;
+    const int64_t c1 = c0 + chunk < npair ? c0 + chunk : npair;
+    const TB* rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rows[r] = B + (P0 + r < naux ? P0 + r : naux - 1) * ldB;
+    Acc<ACC> acc[R];
+    int64_t p = c0;
+    if (vec) {
+        // c0 is a multiple of V and rows are 16-byte aligned
+        for (p = c0 + (int64_t)V * threadIdx.x; p + V <= c1; p += (int64_t)V * kThreads) {
+            double m[V];
+            float mh[V], ml[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                if (ACC == ACC_F64) m[v] = dt[p + v];
+                else {
+                    mh[v] = dhi[p + v];
+                    ml[v] = ACC == ACC_DOT2 ? dlo[p + v] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float b[V];
+                load16<TB>(rows[r] + p, b);
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[r].add(b[v], ACC == ACC_F64 ? m[v] : 0.0, mh[v], ml[v]);
+            }
+        }
+        // the last partial vector of the chunk: element by element
+        p = c0 + ((c1 - c0) / V) * V + threadIdx.x;
+    } else {
+        p = c0 + threadIdx.x;
+    }
+    for (; p < c1; p += kThreads) {
+        const double m = dt[p];
+        const float mh = ACC == ACC_F64 ? 0.f : dhi[p];
+        const float ml = ACC == ACC_DOT2 ? dlo[p] : 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r].add(Elem<TB>::f(rows[r][p]), m, mh, ml);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double sum = block_sum(acc[r].value(), lds);
+        if (threadIdx.x == 0 && P0 + r < naux) part[(P0 + r) * nchunk + c] = sum;
+    }
+}
+
+template <typename TB, int ACC>
+__global__ __launch_bounds__(kThreads) void j_out_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
+                                                       int64_t npair, const double* __restrict__ rho,
+                                                       const float* __restrict__ rhi,
+                                                       const float* __restrict__ rlo, int64_t prows,
+                                                       bool vec, double* __restrict__ jpart) {
+    constexpr int V = Elem<TB>::V;
+    const int s = blockIdx.y;
+    const int64_t P0 = (int64_t)s * prows;
+    const int64_t P1 = P0 + prows < naux ? P0 + prows : naux;
+    const int64_t col0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * V;
+    Acc<ACC> acc[V];
+    if (vec && col0 + V <= npair) {
+#pragma unroll 4
+        for (int64_t P = P0; P < P1; ++P) {
+            const double m = rho[P];
+            const float mh = ACC == ACC_F64 ? 0.f : rhi[P];
+            const float ml = ACC == ACC_DOT2 ? rlo[P] : 0.f;
+            float b[V];
+            load16<TB>(B + P * ldB + col0, b);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v].add(b[v], m, mh, ml);
+        }
+    } else {
+        for (int64_t P = P0; P < P1; ++P) {
+            const double m = rho[P];
+            const float mh = ACC == ACC_F64 ? 0.f : rhi[P];
+            const float ml = ACC == ACC_DOT2 ? rlo[P] : 0.f;
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (col0 + v < npair) acc[v].add(Elem<TB>::f(B[P * ldB + col0 + v]), m, mh, ml);
+        }
+    }
+    double* out = jpart + (int64_t)s * npair;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        if (col0 + v < npair) out[col0 + v] = acc[v].value();
+}
+
+template <typename TB, int ACC>
+int j_build_red_t(dfjk_ctx* h, double* J, double* rho_out) {
+    constexpr int V = Elem<TB>::V;
+    constexpr int R = 8;
+    const TB* B = static_cast<const TB*>(h->B);
+    double* dt = static_cast<double*>(h->dt.ptr);
+    float* dhi = reinterpret_cast<float*>(dt + h->npair);
+    float* dlo = dhi + h->npair;
+    double* part = static_cast<double*>(h->rho_part.ptr);
+    double* rho = static_cast<double*>(h->rho.ptr);
+    float* rhi = reinterpret_cast<float*>(rho + h->naux);
+    float* rlo = rhi + h->naux;
+    double* jpart = static_cast<double*>(h->jpart.ptr);
+    const hipStream_t st = h->stream;
+    if (ACC != ACC_F64) {
+        split_f64<<<dim3((unsigned)cdiv(h->npair, 256)), 256, 0, st>>>(dt, h->npair, dhi, dlo);
+        DFJK_LAUNCH_CHECK("split_f64");
+    }
+    const bool vec = (h->ldB % V == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    int64_t chunk = cdiv(h->npair, h->j_chunks);
+    chunk = cdiv(chunk, V) * V;
+    const dim3 g1((unsigned)cdiv(h->naux, R), (unsigned)h->j_chunks);
+    h->prof.begin(PH_J_RHO, st);
+    j_rho_red<TB, R, ACC><<<g1, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, dt, dhi, dlo, chunk,
+                                                    h->j_chunks, vec, part);
+    h->prof.end(PH_J_RHO, st);
+    DFJK_LAUNCH_CHECK("j_rho_red");
+    j_rho_finish<<<dim3((unsigned)cdiv(h->naux, 256)), 256, 0, st>>>(part, h->naux, h->j_chunks, rho,
+                                                                       rho_out);
+    DFJK_LAUNCH_CHECK("j_rho_finish");
+    if (ACC != ACC_F64) {
+        split_f64<<<dim3((unsigned)cdiv(h->naux, 256)), 256, 0, st>>>(rho, h->naux, rhi, rlo);
+        DFJK_LAUNCH_CHECK("split_f64");
+    }
+    const int64_t prows = cdiv(h->naux, h->j_splits);
+    const dim3 g2((unsigned)cdiv(h->npair, (int64_t)kThreads * V), (unsigned)h->j_splits);
+    h->prof.begin(PH_J_OUT, st);
+    j_out_red<TB, ACC><<<g2, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, rho, rhi, rlo, prows, vec,
+                                                jpart);
+    h->prof.end(PH_J_OUT, st);
+    DFJK_LAUNCH_CHECK("j_out_red");
+    j_finish<<<dim3((unsigned)h->nao), kThreads, 0, st>>>(jpart, h->npair, h->j_splits, h->nao, J);
+    h->prof.end(PH_J, st);
+    DFJK_LAUNCH_CHECK("j_finish");
+    return DFJK_OK;
+}
+
+template <typename TB>
+int j_build_red(dfjk_ctx* h, double* J, double* rho_out) {
+    switch (h->opts.compensated_j) {
+        case ACC_F32: return j_build_red_t<TB, ACC_F32>(h, J, rho_out);
+        case ACC_DOT2: return j_build_red_t<TB, ACC_DOT2>(h, J, rho_out);
+        default: return j_build_red_t<TB, ACC_F64>(h, J, rho_out);
+    }
+}
+
 }  // namespace
 
 int j_setup(dfjk_ctx* h) {
@@ -200,31 +421,27 @@ int j_setup(dfjk_ctx* h) {
     int rc;
     if ((rc = h->dt.ensure(sizeof(double) * (size_t)h->npair * 3))) return rc;
     if ((rc = h->rho_part.ensure(sizeof(double) * (size_t)h->naux * (size_t)chunks))) return rc;
-    if ((rc = h->rho.ensure(sizeof(double) * (size_t)h->naux))) return rc;
+    if ((rc = h->rho.ensure(sizeof(double) * (size_t)h->naux * 2))) return rc;  // rho + FP32 hi/lo
     if ((rc = h->jpart.ensure(sizeof(double) * (size_t)h->npair * (size_t)splits))) return rc;
     return DFJK_OK;
 }
 
-int j_build_reduced(dfjk_ctx* h, const double* D, double* J, double* rho_out) {
-    (void)D;
-    (void)J;
-    (void)rho_out;
-    set_error("J for dtype %d is not built yet", h->dtype);
-    return DFJK_E_DTYPE;
-}
-
 int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out) {
-    if (h->dtype != DFJK_F64) return j_build_reduced(h, D, J, rho_out);
-    const double* B = static_cast<const double*>(h->B);
     double* dt = static_cast<double*>(h->dt.ptr);
-    double* part = static_cast<double*>(h->rho_part.ptr);
-    double* rho = static_cast<double*>(h->rho.ptr);
-    double* jpart = static_cast<double*>(h->jpart.ptr);
     const hipStream_t st = h->stream;
-
     h->prof.begin(PH_J, st);
     pack_density<<<dim3((unsigned)h->nao), dim3(kThreads), 0, st>>>(D, h->nao, dt);
     DFJK_LAUNCH_CHECK("pack_density");
+    switch (h->dtype) {
+        case DFJK_F32: return j_build_red<float>(h, J, rho_out);
+        case DFJK_BF16: return j_build_red<uint16_t>(h, J, rho_out);
+        case DFJK_F16: return j_build_red<_Float16>(h, J, rho_out);
+        default: break;
+    }
+    const double* B = static_cast<const double*>(h->B);
+    double* part = static_cast<double*>(h->rho_part.ptr);
+    double* rho = static_cast<double*>(h->rho.ptr);
+    double* jpart = static_cast<double*>(h->jpart.ptr);
 
     const bool vec = (h->ldB % 2 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
     int64_t chunk = cdiv(h->npair, h->j_chunks);

@@ -23,6 +23,31 @@ namespace dfjk {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One 16x16x4 matrix-core step per element type.  Operands: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].  Result element r of lane l is row
+// row(l, r), column l%16 (measured: the FP64 and FP32 instructions differ).
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+    typedef v4d acc_t;
+    __device__ static acc_t zero() { return v4d{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Mma<float> {
+    typedef v4f acc_t;
+    __device__ static acc_t zero() { return v4f{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 constexpr int kThreads = 256;
 constexpr int KC = 16;      // contraction chunk held in LDS
@@ -35,6 +60,20 @@ __device__ inline int64_t pidx(int64_t a, int64_t b) {
     return hi * (hi + 1) / 2 + lo;
 }
 
+// Storage element of B -> compute type (exact for every pair used here).
+template <typename T, typename TS>
+__device__ inline T to_compute(TS x) {
+    return (T)x;
+}
+template <>
+__device__ inline float to_compute<float, uint16_t>(uint16_t x) {  // bfloat16 bits
+    return __uint_as_float((uint32_t)x << 16);
+}
+template <>
+__device__ inline float to_compute<float, _Float16>(_Float16 x) {
+    return (float)x;
+}
+
 // ---------------------------------------------------------------- GEMM1
 // Workgroup tile: BI = 16*NI rows i (all waves) x BM = 64*WM columns mu
 // (each of the 4 waves owns 16*WM columns).  Per 16-deep nu chunk each thread
@@ -44,10 +83,10 @@ __device__ inline int64_t pidx(int64_t a, int64_t b) {
 // below-diagonal B elements (packed row mu, column nu) advance by a constant
 // per chunk; its above-diagonal B elements (packed row nu, column mu) follow
 // the triangular row starts T(nu + 16) = T(nu) + 16 nu + 136.
-template <int NI, int WM>
+template <typename T, int NI, int WM>
 struct G1Stage {
-    double b[4 * WM];
-    double c[NI];
+    T b[4 * WM];
+    T c[NI];
 };
 
 template <int NI, int WM>
@@ -81,27 +120,27 @@ __device__ inline void g1_addr_init(G1Addr<NI, WM>& ad, int64_t nao, int64_t ldc
     ad.mu_ok_up = mu0 + tid % BM < nao;
 }
 
-template <int NI, int WM>
-__device__ inline void g1_load(G1Stage<NI, WM>& st, const G1Addr<NI, WM>& ad,
-                               const double* __restrict__ Bp, int64_t nao,
-                               const double* __restrict__ C, int64_t nu0, int64_t mu0, int tid) {
+template <typename T, typename TS, int NI, int WM>
+__device__ inline void g1_load(G1Stage<T, NI, WM>& st, const G1Addr<NI, WM>& ad,
+                               const TS* __restrict__ Bp, int64_t nao,
+                               const T* __restrict__ C, int64_t nu0, int64_t mu0, int tid) {
     constexpr int BI = 16 * NI, BM = 64 * WM, ROWS = kThreads / BM;
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
         const int k = (tid + j * kThreads) / BI;
-        st.c[j] = (ad.c_ok[j] && nu0 + k < nao) ? C[ad.c_off[j]] : 0.0;
+        st.c[j] = (ad.c_ok[j] && nu0 + k < nao) ? C[ad.c_off[j]] : T(0);
     }
     if (nu0 + KC <= mu0) {
         // every nu < mu: packed row mu, columns nu0 .. nu0+15
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) st.b[j] = ad.mu_ok_lo[j] ? Bp[ad.lo_off[j]] : 0.0;
+        for (int j = 0; j < 4 * WM; ++j) st.b[j] = ad.mu_ok_lo[j] ? to_compute<T, TS>(Bp[ad.lo_off[j]]) : T(0);
     } else if (nu0 >= mu0 + BM - 1) {
         // every nu >= mu: packed row nu, columns mu0 .. mu0+BM-1
         const int m = tid % BM;
 #pragma unroll
         for (int j = 0; j < 4 * WM; ++j) {
             const int64_t nu = nu0 + tid / BM + ROWS * j;
-            st.b[j] = (nu < nao && ad.mu_ok_up) ? Bp[ad.up_row[j] + mu0 + m] : 0.0;
+            st.b[j] = (nu < nao && ad.mu_ok_up) ? to_compute<T, TS>(Bp[ad.up_row[j] + mu0 + m]) : T(0);
         }
     } else {
         // chunk crossing the diagonal
@@ -109,7 +148,7 @@ __device__ inline void g1_load(G1Stage<NI, WM>& st, const G1Addr<NI, WM>& ad,
         for (int j = 0; j < 4 * WM; ++j) {
             const int k = tid / BM + ROWS * j, m = tid % BM;
             const int64_t nu = nu0 + k, mu = mu0 + m;
-            st.b[j] = (nu < nao && mu < nao) ? Bp[pidx(nu, mu)] : 0.0;
+            st.b[j] = (nu < nao && mu < nao) ? to_compute<T, TS>(Bp[pidx(nu, mu)]) : T(0);
         }
     }
 }
@@ -128,9 +167,9 @@ __device__ inline void g1_addr_next(G1Addr<NI, WM>& ad, int64_t nu0, int64_t ldc
     }
 }
 
-template <int NI, int WM>
-__device__ inline void g1_store(const G1Stage<NI, WM>& st, double (*sC)[16 * NI + 1],
-                                double (*sB)[64 * WM + 1], bool lower, int tid) {
+template <typename T, int NI, int WM>
+__device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[16 * NI + 1],
+                                T (*sB)[64 * WM + 1], bool lower, int tid) {
     constexpr int BI = 16 * NI, BM = 64 * WM, ROWS = kThreads / BM;
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
@@ -160,33 +199,32 @@ __device__ inline int64_t xcd_logical(int64_t hw, int64_t nblk) {
 
 // X[(P*ncol + i)*ldx + mu] = sum_nu C[nu][i] B_P[nu][mu]
 // 1-D grid of nib * nmb * naux blocks; logical id -> (i block fastest, mu block, P)
-template <int NI, int WM>
-__global__ __launch_bounds__(kThreads) void k_gemm1_f64(const double* __restrict__ B, int64_t ldB,
-                                                         int64_t nao, const double* __restrict__ C,
-                                                         int64_t ldc, int64_t ncol,
-                                                         double* __restrict__ X, int64_t ldx,
-                                                         int64_t nib, int64_t nmb, int64_t nblk) {
+template <typename T, typename TS, int NI, int WM>
+__global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
+                                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
+                                                     T* __restrict__ X, int64_t ldx, int64_t nib,
+                                                     int64_t nmb, int64_t nblk) {
     constexpr int BI = 16 * NI, BM = 64 * WM;
-    __shared__ double sC[2][KC][BI + 1];
-    __shared__ double sB[2][KC][BM + 1];
+    __shared__ T sC[2][KC][BI + 1];
+    __shared__ T sB[2][KC][BM + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t lid = xcd_logical(blockIdx.x, nblk);
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, mu0 = mb * BM;
-    const double* Bp = B + P * ldB;
+    const TS* Bp = B + P * ldB;
 
-    v4d acc[NI][WM];
+    typename Mma<T>::acc_t acc[NI][WM];
 #pragma unroll
     for (int a = 0; a < NI; ++a)
 #pragma unroll
-        for (int b = 0; b < WM; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < WM; ++b) acc[a][b] = Mma<T>::zero();
 
     const int64_t nchunks = cdiv(nao, KC);
-    G1Stage<NI, WM> st;
+    G1Stage<T, NI, WM> st;
     G1Addr<NI, WM> ad;
     g1_addr_init<NI, WM>(ad, nao, ldc, ncol, mu0, i0, tid);
-    g1_load<NI, WM>(st, ad, Bp, nao, C, 0, mu0, tid);
-    g1_store<NI, WM>(st, sC[0], sB[0], KC <= mu0, tid);
+    g1_load<T, TS, NI, WM>(st, ad, Bp, nao, C, 0, mu0, tid);
+    g1_store<T, NI, WM>(st, sC[0], sB[0], KC <= mu0, tid);
     __syncthreads();
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
@@ -194,12 +232,12 @@ __global__ __launch_bounds__(kThreads) void k_gemm1_f64(const double* __restrict
         const bool more = ch + 1 < nchunks;
         if (more) {
             g1_addr_next<NI, WM>(ad, ch * KC, ldc, tid);
-            g1_load<NI, WM>(st, ad, Bp, nao, C, nnext, mu0, tid);
+            g1_load<T, TS, NI, WM>(st, ad, Bp, nao, C, nnext, mu0, tid);
         }
 #pragma unroll
         for (int kk = 0; kk < KC / 4; ++kk) {
             const int kr = kk * 4 + (lane >> 4);
-            double a[NI], b[WM];
+            T a[NI], b[WM];
 #pragma unroll
             for (int t = 0; t < NI; ++t) a[t] = sC[buf][kr][t * 16 + (lane & 15)];
 #pragma unroll
@@ -207,32 +245,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm1_f64(const double* __restrict
 #pragma unroll
             for (int ti = 0; ti < NI; ++ti)
 #pragma unroll
-                for (int tj = 0; tj < WM; ++tj)
-                    acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+                for (int tj = 0; tj < WM; ++tj) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
         }
-        if (more) g1_store<NI, WM>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
+        if (more) g1_store<T, NI, WM>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
         __syncthreads();
     }
-    // v_mfma_f64_16x16x4f64 result: lane l, element r holds row 4*r + l/16,
-    // column l%16 of the 16x16 tile (operands: A[l%16][l/16], B[l/16][l%16])
 #pragma unroll
     for (int ti = 0; ti < NI; ++ti)
 #pragma unroll
         for (int tj = 0; tj < WM; ++tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + ti * 16 + 4 * r + (lane >> 4);
+                const int64_t i = i0 + ti * 16 + Mma<T>::row(lane, r);
                 const int64_t mu = mu0 + wave * 16 * WM + tj * 16 + (lane & 15);
                 if (i < ncol && mu < nao) X[(P * ncol + i) * ldx + mu] = acc[ti][tj][r];
             }
 }
 
 // ---------------------------------------------------------------- GEMM2 (SYRK)
+template <typename T>
 struct SyStage {
-    double a[8], b[8];
+    T a[8], b[8];
 };
 
-__device__ inline void sy_load(SyStage& st, const double* __restrict__ X, int64_t ldx, int64_t nrows,
+template <typename T>
+__device__ inline void sy_load(SyStage<T>& st, const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                int64_t nao, int64_t ncol, const double* __restrict__ sign, int64_t k0,
                                int64_t kend, int64_t mu0, int64_t nu0, int tid) {
 #pragma unroll
@@ -240,23 +277,23 @@ __device__ inline void sy_load(SyStage& st, const double* __restrict__ X, int64_
         const int k = tid / SY_T + 2 * j, m = tid % SY_T;
         const int64_t row = k0 + k;
         const bool ok = row < kend;
-        const double* xr = X + row * ldx;
-        st.a[j] = (ok && mu0 + m < nao) ? xr[mu0 + m] : 0.0;
-        double bv = (ok && nu0 + m < nao) ? xr[nu0 + m] : 0.0;
-        if (sign && ok) bv *= sign[row % ncol];
+        const T* xr = X + row * ldx;
+        st.a[j] = (ok && mu0 + m < nao) ? xr[mu0 + m] : T(0);
+        T bv = (ok && nu0 + m < nao) ? xr[nu0 + m] : T(0);
+        if (sign && ok && sign[row % ncol] < 0) bv = -bv;
         st.b[j] = bv;
     }
 }
 
 // partial[(s*ntl + t)][m][n] = sum_{k in split s} X[k][mu0+m] * sign_k * X[k][nu0+n]
 // grid: x = lower tile t (I >= J), y = split s
-__global__ __launch_bounds__(kThreads) void k_syrk_f64(const double* __restrict__ X, int64_t ldx,
-                                                        int64_t nrows, int64_t nao, int64_t ncol,
-                                                        const double* __restrict__ sign,
-                                                        int64_t kchunk, int64_t ntl, int64_t nblk,
-                                                        double* __restrict__ part) {
-    __shared__ double sA[2][KC][SY_T + 1];
-    __shared__ double sB[2][KC][SY_T + 1];
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int64_t ldx, int64_t nrows,
+                                                    int64_t nao, int64_t ncol,
+                                                    const double* __restrict__ sign, int64_t kchunk,
+                                                    int64_t ntl, int64_t nblk, T* __restrict__ part) {
+    __shared__ T sA[2][KC][SY_T + 1];
+    __shared__ T sB[2][KC][SY_T + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     // all tiles of one split run on one XCD and share its L2 copy of the X rows
@@ -271,15 +308,15 @@ __global__ __launch_bounds__(kThreads) void k_syrk_f64(const double* __restrict_
     const int64_t kbeg = s * kchunk;
     const int64_t kend = kbeg + kchunk < nrows ? kbeg + kchunk : nrows;
 
-    v4d acc[4][4];
+    typename Mma<T>::acc_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mma<T>::zero();
 
     if (kbeg < kend) {
         const int64_t nchunks = cdiv(kend - kbeg, KC);
-        SyStage st;
+        SyStage<T> st;
         sy_load(st, X, ldx, nrows, nao, ncol, sign, kbeg, kend, mu0, nu0, tid);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -294,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_syrk_f64(const double* __restrict_
 #pragma unroll
             for (int kk = 0; kk < KC / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
-                double a[4], b[4];
+                T a[4], b[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     a[q] = sA[buf][kr][wm * 64 + q * 16 + (lane & 15)];
@@ -303,8 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_syrk_f64(const double* __restrict_
 #pragma unroll
                 for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < 4; ++tj)
-                        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+                    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
             }
             if (more) {
 #pragma unroll
@@ -316,14 +352,14 @@ __global__ __launch_bounds__(kThreads) void k_syrk_f64(const double* __restrict_
             __syncthreads();
         }
     }
-    double* out = part + (s * ntl + t) * (int64_t)(SY_T * SY_T);
+    T* out = part + (s * ntl + t) * (int64_t)(SY_T * SY_T);
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 4; ++tj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int m = wm * 64 + ti * 16 + 4 * r + (lane >> 4);
+                const int m = wm * 64 + ti * 16 + Mma<T>::row(lane, r);
                 const int n = wn * 64 + tj * 16 + (lane & 15);
                 out[m * SY_T + n] = acc[ti][tj][r];
             }
@@ -331,7 +367,8 @@ __global__ __launch_bounds__(kThreads) void k_syrk_f64(const double* __restrict_
 
 // K[mu][nu] = K[nu][mu] = scale * sum_s partial[s][t][m][n] over the lower
 // triangle (on diagonal tiles only m >= n is used, so K is exactly symmetric).
-__global__ __launch_bounds__(kThreads) void k_syrk_finish(const double* __restrict__ part,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ part,
                                                            int64_t nsplit, int64_t ntl, int64_t nao,
                                                            double scale, double* __restrict__ K) {
     const int64_t t = blockIdx.x;
@@ -345,35 +382,51 @@ __global__ __launch_bounds__(kThreads) void k_syrk_finish(const double* __restri
         if (mu >= nao || nu >= nao) continue;
         if (I == J && m < n) continue;
         double v = 0.0;
-        for (int64_t s = 0; s < nsplit; ++s) v += part[(s * ntl + t) * (int64_t)(SY_T * SY_T) + e];
+        for (int64_t s = 0; s < nsplit; ++s) v += (double)part[(s * ntl + t) * (int64_t)(SY_T * SY_T) + e];
         v *= scale;
         K[mu * nao + nu] = v;
         K[nu * nao + mu] = v;
     }
 }
 
-template <int NI, int WM>
-int launch_gemm1(const dfjk_ctx* h, const double* C, int64_t ncol, double* X, int64_t ldx) {
+template <typename T, typename TS, int NI, int WM>
+int launch_gemm1(const dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx) {
     const int64_t nib = cdiv(ncol, 16 * NI), nmb = cdiv(h->nao, 64 * WM);
     const int64_t nblk = nib * nmb * h->naux;
-    k_gemm1_f64<NI, WM><<<dim3((unsigned)nblk), kThreads, 0, h->stream>>>(
-        static_cast<const double*>(h->B), h->ldB, h->nao, C, ncol, ncol, X, ldx, nib, nmb, nblk);
-    DFJK_LAUNCH_CHECK("k_gemm1_f64");
+    k_gemm1<T, TS, NI, WM><<<dim3((unsigned)nblk), kThreads, 0, h->stream>>>(
+        static_cast<const TS*>(h->B), h->ldB, h->nao, static_cast<const T*>(C), ncol, ncol,
+        static_cast<T*>(X), ldx, nib, nmb, nblk);
+    DFJK_LAUNCH_CHECK("k_gemm1");
     return DFJK_OK;
 }
 
-// Compiled GEMM1 tiles: (NI, WM) = (i tiles of 16, mu tiles of 16 per wave).
+// Compiled GEMM1 tiles: (NI, WM) = (i tiles of 16, mu tiles of 16 per wave),
+// one launcher per B storage type (FP64 on the FP64 matrix cores; FP32, BF16
+// and FP16 dequantised exactly on load and run on the FP32 matrix cores).
+typedef int (*G1Launch)(const dfjk_ctx*, const void*, int64_t, void*, int64_t);
 struct G1Tile {
     int ni, wm;
-    int (*launch)(const dfjk_ctx*, const double*, int64_t, double*, int64_t);
+    G1Launch by_dtype[4];  // indexed by dfjk_dtype
 };
+#define G1T(a, b)                                                                              \
+    {                                                                                          \
+        a, b, {                                                                                \
+            launch_gemm1<double, double, a, b>, launch_gemm1<float, float, a, b>,              \
+                launch_gemm1<float, uint16_t, a, b>, launch_gemm1<float, _Float16, a, b>       \
+        }                                                                                      \
+    }
 const G1Tile kG1Tiles[] = {
-    {1, 2, launch_gemm1<1, 2>}, {2, 2, launch_gemm1<2, 2>}, {3, 2, launch_gemm1<3, 2>},
-    {4, 2, launch_gemm1<4, 2>}, {5, 2, launch_gemm1<5, 2>}, {6, 2, launch_gemm1<6, 2>},
-    {7, 2, launch_gemm1<7, 2>}, {8, 2, launch_gemm1<8, 2>}, {13, 1, launch_gemm1<13, 1>},
-    {4, 4, launch_gemm1<4, 4>}, {7, 1, launch_gemm1<7, 1>}, {5, 1, launch_gemm1<5, 1>},
+    G1T(1, 2), G1T(2, 2), G1T(3, 2), G1T(4, 2), G1T(5, 2), G1T(6, 2),
+    G1T(7, 2), G1T(8, 2), G1T(13, 1), G1T(4, 4), G1T(7, 1), G1T(5, 1),
 };
+#undef G1T
 constexpr int kNumG1Tiles = sizeof(kG1Tiles) / sizeof(kG1Tiles[0]);
+
+// FP64 -> FP32 copy of C (one rounding per element).
+__global__ void to_f32(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
 
 // Default tile: least padded work, where each extra i block costs another
 // read of the B tile (weight 1/2 of a padded column block), among the tiles
@@ -395,24 +448,18 @@ int pick_g1_tile(int64_t ncol) {
     return best;
 }
 
-}  // namespace
-
-int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
-                     double* K) {
-    if (h->dtype != DFJK_F64) {
-        set_error("K for dtype %d is not built yet", h->dtype);
-        return DFJK_E_DTYPE;
-    }
+template <typename T>
+int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, double scale, double* K) {
     const int64_t ldx = h->nao;
     const int64_t nrows = h->naux * ncol;
     int rc;
-    if ((rc = h->X.ensure(sizeof(double) * (size_t)nrows * (size_t)ldx))) return rc;
-    double* X = static_cast<double*>(h->X.ptr);
+    if ((rc = h->X.ensure(sizeof(T) * (size_t)nrows * (size_t)ldx))) return rc;
+    T* X = static_cast<T*>(h->X.ptr);
 
     h->prof.begin(PH_K, h->stream);
     h->prof.begin(PH_K_GEMM1, h->stream);
-    int tile = h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles ? h->g1_tile : pick_g1_tile(ncol);
-    rc = kG1Tiles[tile].launch(h, C, ncol, X, ldx);
+    const int tile = h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles ? h->g1_tile : pick_g1_tile(ncol);
+    rc = kG1Tiles[tile].by_dtype[h->dtype](h, C, ncol, X, ldx);
     h->prof.end(PH_K_GEMM1, h->stream);
     if (rc) return rc;
 
@@ -424,19 +471,34 @@ int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* s
     if (nsplit < 1) nsplit = 1;
     int64_t kchunk = cdiv(cdiv(nrows, nsplit), KC) * KC;
     nsplit = cdiv(nrows, kchunk);
-    if ((rc = h->kpart.ensure(sizeof(double) * (size_t)(nsplit * ntl) * SY_T * SY_T))) return rc;
-    double* part = static_cast<double*>(h->kpart.ptr);
+    if ((rc = h->kpart.ensure(sizeof(T) * (size_t)(nsplit * ntl) * SY_T * SY_T))) return rc;
+    T* part = static_cast<T*>(h->kpart.ptr);
     h->prof.begin(PH_K_SYRK, h->stream);
-    k_syrk_f64<<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
+    k_syrk<T><<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
         X, ldx, nrows, h->nao, ncol, sign, kchunk, ntl, ntl * nsplit, part);
     h->prof.end(PH_K_SYRK, h->stream);
-    DFJK_LAUNCH_CHECK("k_syrk_f64");
+    DFJK_LAUNCH_CHECK("k_syrk");
     h->prof.begin(PH_K_FINISH, h->stream);
-    k_syrk_finish<<<dim3((unsigned)ntl), kThreads, 0, h->stream>>>(part, nsplit, ntl, h->nao, scale, K);
+    k_syrk_finish<T><<<dim3((unsigned)ntl), kThreads, 0, h->stream>>>(part, nsplit, ntl, h->nao, scale, K);
     h->prof.end(PH_K_FINISH, h->stream);
     h->prof.end(PH_K, h->stream);
     DFJK_LAUNCH_CHECK("k_syrk_finish");
     return DFJK_OK;
+}
+
+}  // namespace
+
+int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
+                     double* K) {
+    if (h->dtype == DFJK_F64) return k_build_t<double>(h, C, ncol, sign, scale, K);
+    {  // FP32 compute for FP32, BF16 and FP16 storage of B
+        int rc;
+        if ((rc = h->Cw.ensure(sizeof(float) * (size_t)(h->nao * ncol)))) return rc;
+        float* Cf = static_cast<float*>(h->Cw.ptr);
+        to_f32<<<dim3((unsigned)cdiv(h->nao * ncol, 256)), 256, 0, h->stream>>>(C, h->nao * ncol, Cf);
+        DFJK_LAUNCH_CHECK("to_f32");
+        return k_build_t<float>(h, Cf, ncol, sign, scale, K);
+    }
 }
 
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
