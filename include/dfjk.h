@@ -71,7 +71,8 @@ typedef struct {
     double conv_tol;      /* |E_k - E_{k-1}| threshold (1e-9) */
     double conv_tol_grad; /* ||FD - DF||_F threshold (3e-5) */
     int max_cycle;        /* SCF iteration cap (100) */
-    int compensated_j;    /* reduced-precision B: 1 = two-term FP32 sums in J (1) */
+    int compensated_j;    /* reduced-precision B, J accumulation: 2 = FP64 (default),
+                             1 = compensated FP32 (Dot2), 0 = plain FP32 */
 } dfjk_options;
 
 /* Fills *o with the defaults. */
@@ -112,6 +113,43 @@ int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_
 int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const double* D_dev,
                  double* K_dev);
 
+/* One SCF iteration's record (host struct). */
+typedef struct {
+    double e_tot;    /* E_k = tr(D H) + tr(D J)/2 - tr(D K)/4 of the input density */
+    double e_1e;     /* tr(D H) */
+    double e_j;      /* tr(D J)/2 = (1/2) sum_P rho_P^2 */
+    double e_k;      /* -tr(D K)/4 */
+    double err_norm; /* ||F D - D F||_F */
+    double d_e;      /* E_k - E_{k-1} (E_1 on the first iteration) */
+    int iter;        /* k, counted from 1 since the last dfjk_scf_reset */
+    int converged;   /* k > 1, |d_e| < conv_tol and err_norm < conv_tol_grad */
+} dfjk_scf_info;
+
+/* dfjk_scf_step flag: on entry Cocc_dev holds orbitals with D = 2 C C^T. */
+enum { DFJK_SCF_C_VALID = 1 };
+
+/*
+ * One restricted closed-shell SCF iteration in an orthonormal AO basis
+ * (paper Sec. IV.A: a mean-field run starts from a guess density, which need
+ * not be idempotent; Sec. IV.B: Pulay DIIS is the default accelerator):
+ *   J, K of D (K through Cocc when flags has DFJK_SCF_C_VALID, else through
+ *   the eigen-factors of D); F = H + J - K/2; E = tr(D(H+F))/2;
+ *   e = FD - DF; DIIS over the last diis_space (F, e) pairs; aufbau on the
+ *   extrapolated F; D <- 2 C C^T, Cocc <- C (nao x nocc).
+ *   H_dev    nao x nao FP64 core Hamiltonian (symmetric).
+ *   D_dev    in: the density of this iteration; out: the next density.
+ *   Cocc_dev out: the next occupied orbitals (in: see flags).
+ *   info     host pointer or NULL.  When given, the call waits for the stream,
+ *            fills it, and returns DFJK_W_NOT_CONVERGED until converged.
+ * nao <= 4096.  Iteration count and DIIS history live in the handle; call
+ * dfjk_scf_reset before starting another system.
+ */
+int dfjk_scf_step(dfjk_handle h, const double* H_dev, double* D_dev, double* Cocc_dev, int64_t nocc,
+                  int flags, dfjk_scf_info* info);
+
+/* Forget the SCF iteration count and the DIIS history. */
+int dfjk_scf_reset(dfjk_handle h);
+
 /*
  * Exchange with per-column signs: K = s * sum_P sum_i sign_i X_P[:,i] X_P[:,i]^T,
  * X_P = B_P C, sign_dev[i] in {+1, -1} (FP64, nocc entries, NULL = all +1).
@@ -145,6 +183,80 @@ enum { DFJK_TILE_GEMM1 = 0 };
 int dfjk_tile_count(int kernel);
 int dfjk_tile_info(int kernel, int index, int* p0, int* p1);
 int dfjk_set_tile(dfjk_handle h, int kernel, int index);
+
+/*
+ * Batched builds: J and K for many molecules of uneven size in one pass
+ * (each phase of the build is one launch over every molecule; molecules are
+ * dispatched longest first).  Per molecule (all device pointers, held by the
+ * caller for the life of the batch; contents may change between builds):
+ *   B (naux x ldB packed, element type `dtype` = DFJK_F32, DFJK_BF16 or
+ *   DFJK_F16), D and J, K (nao x nao FP64), Cocc (nao x nocc FP64).
+ * Each build writes J(D) and K = 2 sum_P (B_P C)(B_P C)^T for every molecule;
+ * J accumulates in FP64, the K products run on the FP32 matrix cores.
+ *   dfjk_batch_build    enqueue the whole batch on the stream.
+ *   dfjk_batch_capture  record one build into a HIP graph (no allocation,
+ *                       synchronisation or memset inside a build).
+ *   dfjk_batch_launch   replay the recorded graph on the stream.
+ *   dfjk_batch_autotune time every compiled GEMM1 tile per bucket of
+ *                       molecules (bucket = ceil(nocc/16) - 1, 0..7), keep the
+ *                       fastest whose K matches the default tile's within
+ *                       1e-5 relative, and store the choice in cache_path
+ *                       (text lines "dtype bucket tile ms"; read instead of
+ *                       timing when present).  best_ms (8 doubles) or NULL.
+ *                       Drops a recorded graph.
+ */
+typedef struct dfjk_batch_ctx* dfjk_batch;
+typedef struct {
+    const void* B;
+    int64_t nao, naux, ldB, nocc;
+    const double* D;
+    const double* Cocc;
+    double* J;
+    double* K;
+} dfjk_mol;
+int dfjk_batch_init(dfjk_batch* b, const dfjk_mol* mols, int nmol, int dtype, void* stream);
+int dfjk_batch_build(dfjk_batch b);
+int dfjk_batch_capture(dfjk_batch b);
+int dfjk_batch_launch(dfjk_batch b);
+int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* best_ms);
+int dfjk_batch_get_tile(dfjk_batch b, int bucket, int* tile);
+int dfjk_batch_set_tile(dfjk_batch b, int bucket, int tile);
+int dfjk_batch_workspace_bytes(dfjk_batch b, size_t* bytes);
+void dfjk_batch_destroy(dfjk_batch b);
+
+/*
+ * Learned initial guess (a guess density need not be idempotent, paper
+ * Sec. IV.A.1).  A perceptron d_in -> hidden -> hidden -> 1 with SiLU
+ * activations, FP32, trained on the GPU:
+ *   dfjk_mlp_init        allocate for batches of up to max_batch rows.
+ *   dfjk_mlp_nparam      number of FP32 parameters, laid out as
+ *                        W1 (hidden x d_in), b1, W2 (hidden x hidden), b2,
+ *                        W3 (hidden), b3, each row-major.
+ *   dfjk_mlp_set_params  upload parameters (host array) and clear Adam state.
+ *   dfjk_mlp_get         download parameters (which = 0) or the gradient of
+ *                        the last dfjk_mlp_loss_grad (which = 1); waits.
+ *   dfjk_mlp_forward     y = f(X) for n rows (X: n x d_in FP32, device).
+ *   dfjk_mlp_loss_grad   L = mean((f(X) - t)^2) and its gradient (kept in
+ *                        the handle); L to loss_dev (device, may be NULL).
+ *   dfjk_mlp_adam        one Adam step (Kingma & Ba) with the kept gradient.
+ * Features and guess for one system (nao <= 65535, device pointers):
+ *   dfjk_guess_features  X (npair x 8 FP32, packed pair order) from H, the
+ *                        core-guess density Dcore and positions R (nao x 3).
+ *   dfjk_guess_assemble  D = Dcore + y, symmetric, from y (npair FP32).
+ */
+typedef struct dfjk_mlp_ctx* dfjk_mlp;
+int dfjk_mlp_init(dfjk_mlp* m, int d_in, int hidden, int64_t max_batch, void* stream);
+int64_t dfjk_mlp_nparam(dfjk_mlp m);
+int dfjk_mlp_set_params(dfjk_mlp m, const float* host_params);
+int dfjk_mlp_get(dfjk_mlp m, int which, float* host_out);
+int dfjk_mlp_forward(dfjk_mlp m, const float* X_dev, int64_t n, float* y_dev);
+int dfjk_mlp_loss_grad(dfjk_mlp m, const float* X_dev, const float* t_dev, int64_t n, float* loss_dev);
+int dfjk_mlp_adam(dfjk_mlp m, float lr, float beta1, float beta2, float eps);
+void dfjk_mlp_destroy(dfjk_mlp m);
+int dfjk_guess_features(const double* H_dev, const double* Dcore_dev, const double* R_dev, int64_t nao,
+                        float* X_dev, void* stream);
+int dfjk_guess_assemble(const float* y_dev, const double* Dcore_dev, int64_t nao, double* D_dev,
+                        void* stream);
 
 /* Device workspace currently held by the handle, in bytes. */
 int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes);

@@ -59,7 +59,7 @@ void dfjk_default_options(dfjk_options* o) {
     o->conv_tol = 1e-9;
     o->conv_tol_grad = 3e-5;
     o->max_cycle = 100;
-    o->compensated_j = 1;
+    o->compensated_j = 2;
 }
 
 const char* dfjk_last_error(void) { return g_err; }
@@ -116,6 +116,12 @@ int dfjk_init(dfjk_handle* out, const void* B_dev, int dtype, int64_t nao, int64
         h->opts = *opts;
     else
         dfjk_default_options(&h->opts);
+    if (h->opts.diis_space < 1 || h->opts.diis_space > 15 || h->opts.max_cycle < 1 ||
+        h->opts.compensated_j < 0 || h->opts.compensated_j > 2) {
+        delete h;
+        set_error("dfjk_init: options out of range (diis_space 1..15, compensated_j 0..2)");
+        return DFJK_E_INVALID;
+    }
     int rc = j_setup(h);
     if (rc != DFJK_OK) {
         dfjk_destroy(h);
@@ -172,6 +178,32 @@ int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const doub
         return DFJK_E_INVALID;
     }
     return k_build_from_D(h, D_dev, K_dev);
+}
+
+int dfjk_scf_step(dfjk_handle h, const double* H_dev, double* D_dev, double* Cocc_dev, int64_t nocc,
+                  int flags, dfjk_scf_info* info) {
+    static_assert(sizeof(dfjk_scf_info) == 6 * sizeof(double) + 2 * sizeof(int), "record layout");
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!H_dev || !D_dev || !Cocc_dev) {
+        set_error("dfjk_scf_step: null H, D or Cocc");
+        return DFJK_E_INVALID;
+    }
+    if (nocc < 1 || nocc > h->nao) {
+        set_error("dfjk_scf_step: nocc=%lld outside [1, nao=%lld]", (long long)nocc, (long long)h->nao);
+        return DFJK_E_INVALID;
+    }
+    if (flags & ~DFJK_SCF_C_VALID) {
+        set_error("dfjk_scf_step: unknown flags 0x%x", flags);
+        return DFJK_E_INVALID;
+    }
+    return scf_step(h, H_dev, D_dev, Cocc_dev, nocc, flags, info);
+}
+
+int dfjk_scf_reset(dfjk_handle h) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    return scf_reset(h);
 }
 
 int dfjk_tile_count(int kernel) {

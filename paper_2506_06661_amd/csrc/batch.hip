@@ -1,0 +1,489 @@
+// Batched J/K builds over many molecules of uneven size.
+//
+// Every phase of the single-molecule build (pack density, J pass 1, rho
+// reduction, J pass 2, J unpack, C to FP32, GEMM1, SYRK, K reduction) runs as
+// ONE launch over all molecules: the grid is the concatenation of every
+// molecule's blocks, molecules in longest-processing-time-first order (cost
+// naux * nao^2 * nocc), and each block finds its molecule by binary search in
+// a prefix table.  GEMM1 runs once per tile bucket (molecules grouped by
+// ceil(nocc/16)), with the tile of each bucket chosen by the autotuner.  The
+// whole sequence can be captured once into a HIP graph and replayed: no
+// allocation, host synchronisation or memset is enqueued by a build.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace dfjk {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kBuckets = 8;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int bucket_of(int64_t nocc) {
+    const int64_t b = cdiv(nocc, 16) - 1;
+    return (int)(b < kBuckets - 1 ? b : kBuckets - 1);
+}
+
+struct Phase {
+    int kind;  // BatchPhaseKind, or -1 for GEMM1
+    int bucket;
+    std::vector<int> ids;
+    std::vector<int64_t> prefix;
+    int64_t off_ids = 0, off_prefix = 0;  // byte offsets in the list buffer
+};
+
+}  // namespace
+}  // namespace dfjk
+
+struct dfjk_batch_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;  // private stream for graph capture
+    int dtype = DFJK_F32;
+    int nmol = 0;
+    std::vector<dfjk::MolDesc> mols;
+    std::vector<double> cost;
+    std::vector<int> order;  // molecules, longest first
+    dfjk::DevBuf d_mols, work, lists;
+    std::vector<dfjk::Phase> phases;
+    int tile[dfjk::kBuckets];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace dfjk {
+namespace {
+
+int64_t phase_blocks(int kind, const MolDesc& d, int dtype) {
+    const int64_t V = dtype == DFJK_F32 ? 4 : 8;
+    switch (kind) {
+        case BP_PACK: return d.nao;
+        case BP_RHO: return cdiv(d.naux, 8) * d.j_chunks;
+        case BP_RHO_FIN: return cdiv(d.naux, kT);
+        case BP_OUT: return cdiv(d.npair, kT * V) * d.j_splits;
+        case BP_JFIN: return d.nao;
+        case BP_CF32: return cdiv(d.nao * d.nocc, kT);
+        case BP_SYRK: return d.ntl * d.nsplit;
+        case BP_KFIN: return d.ntl;
+        default: return 0;
+    }
+}
+
+// (Re)build the GEMM1 geometry and the phase lists for the current tiles.
+int build_phases(dfjk_batch_ctx* b) {
+    for (auto& d : b->mols) {
+        const int t = b->tile[bucket_of(d.nocc)];
+        tile_nb(t, d.nao, d.nocc, &d.g1_nib, &d.g1_nmb);
+    }
+    b->phases.clear();
+    auto add = [&](int kind, int bucket) {
+        Phase ph;
+        ph.kind = kind;
+        ph.bucket = bucket;
+        int64_t acc = 0;
+        for (int m : b->order) {
+            const MolDesc& d = b->mols[m];
+            int64_t nb;
+            if (kind < 0) {
+                if (bucket_of(d.nocc) != bucket) continue;
+                nb = d.g1_nib * d.g1_nmb * d.naux;
+            } else {
+                nb = phase_blocks(kind, d, b->dtype);
+            }
+            ph.ids.push_back(m);
+            ph.prefix.push_back(acc);
+            acc += nb;
+        }
+        ph.prefix.push_back(acc);
+        if (!ph.ids.empty()) b->phases.push_back(ph);
+    };
+    for (int k : {BP_PACK, BP_RHO, BP_RHO_FIN, BP_OUT, BP_JFIN, BP_CF32}) add(k, 0);
+    for (int bk = 0; bk < kBuckets; ++bk) add(-1, bk);
+    for (int k : {BP_SYRK, BP_KFIN}) add(k, 0);
+    size_t bytes = 0;
+    for (auto& ph : b->phases) {
+        ph.off_ids = (int64_t)bytes;
+        bytes += (ph.ids.size() * sizeof(int) + 255) / 256 * 256;
+        ph.off_prefix = (int64_t)bytes;
+        bytes += (ph.prefix.size() * sizeof(int64_t) + 255) / 256 * 256;
+    }
+    int rc = b->lists.ensure(bytes);
+    if (rc) return rc;
+    char* base = static_cast<char*>(b->lists.ptr);
+    for (auto& ph : b->phases) {
+        DFJK_HIP_TRY(hipMemcpy(base + ph.off_ids, ph.ids.data(), ph.ids.size() * sizeof(int),
+                               hipMemcpyHostToDevice));
+        DFJK_HIP_TRY(hipMemcpy(base + ph.off_prefix, ph.prefix.data(), ph.prefix.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice));
+    }
+    DFJK_HIP_TRY(hipMemcpy(b->d_mols.ptr, b->mols.data(), b->mols.size() * sizeof(MolDesc),
+                           hipMemcpyHostToDevice));
+    return DFJK_OK;
+}
+
+PhaseList list_of(const dfjk_batch_ctx* b, const Phase& ph) {
+    const char* base = static_cast<const char*>(b->lists.ptr);
+    PhaseList pl;
+    pl.ids = reinterpret_cast<const int*>(base + ph.off_ids);
+    pl.prefix = reinterpret_cast<const int64_t*>(base + ph.off_prefix);
+    pl.n = (int)ph.ids.size();
+    pl.nblk = ph.prefix.back();
+    return pl;
+}
+
+int run_phase(dfjk_batch_ctx* b, const Phase& ph, hipStream_t st) {
+    const MolDesc* mols = static_cast<const MolDesc*>(b->d_mols.ptr);
+    const PhaseList pl = list_of(b, ph);
+    if (ph.kind < 0) return k_batch_gemm1(st, b->dtype, b->tile[ph.bucket], mols, pl);
+    if (ph.kind <= BP_JFIN) return j_batch_phase(st, ph.kind, b->dtype, mols, pl);
+    return k_batch_phase(st, ph.kind, b->dtype, mols, pl);
+}
+
+int run_all(dfjk_batch_ctx* b, hipStream_t st) {
+    for (const auto& ph : b->phases)
+        if (int rc = run_phase(b, ph, st)) return rc;
+    return DFJK_OK;
+}
+
+void drop_graph(dfjk_batch_ctx* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+}  // namespace dfjk
+
+using namespace dfjk;
+
+extern "C" {
+
+int dfjk_batch_init(dfjk_batch* out, const dfjk_mol* mols, int nmol, int dtype, void* stream) {
+    clear_error();
+    if (!out || !mols || nmol < 1 || nmol > (1 << 20)) {
+        set_error("dfjk_batch_init: null pointer or nmol=%d out of range", nmol);
+        return DFJK_E_INVALID;
+    }
+    *out = nullptr;
+    if (dtype != DFJK_F32 && dtype != DFJK_BF16 && dtype != DFJK_F16) {
+        set_error("dfjk_batch_init: dtype %d; batched builds take FP32, BF16 or FP16 B", dtype);
+        return DFJK_E_DTYPE;
+    }
+    for (int i = 0; i < nmol; ++i) {
+        const dfjk_mol& m = mols[i];
+        const int64_t npair = m.nao * (m.nao + 1) / 2;
+        if (!m.B || !m.D || !m.Cocc || !m.J || !m.K || m.nao < 1 || m.nao > 65535 || m.naux < 1 ||
+            m.ldB < npair || m.nocc < 1 || m.nocc > m.nao) {
+            set_error("dfjk_batch_init: molecule %d has a null pointer or sizes out of range", i);
+            return DFJK_E_INVALID;
+        }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error("dfjk_batch_init: no HIP device available");
+        return DFJK_E_NO_DEVICE;
+    }
+    dfjk_batch_ctx* b = new (std::nothrow) dfjk_batch_ctx();
+    if (!b) {
+        set_error("dfjk_batch_init: host allocation failed");
+        return DFJK_E_OOM;
+    }
+    (void)hipGetDevice(&b->device);
+    b->stream = (hipStream_t)stream;
+    b->dtype = dtype;
+    b->nmol = nmol;
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        set_error("dfjk_batch_init: hipStreamCreate failed");
+        return DFJK_E_HIP;
+    }
+    const int64_t V = dtype == DFJK_F32 ? 4 : 8;
+    const size_t esz = dtype == DFJK_F32 ? 4 : 2;
+    // per-molecule geometry and workspace layout
+    size_t total = 0;
+    auto take = [&](size_t bytes) {
+        const size_t off = total;
+        total += (bytes + 255) / 256 * 256;
+        return off;
+    };
+    std::vector<size_t> offs;
+    b->mols.resize(nmol);
+    for (int i = 0; i < nmol; ++i) {
+        const dfjk_mol& m = mols[i];
+        MolDesc& d = b->mols[i];
+        d = MolDesc{};
+        d.B = m.B;
+        d.ldB = m.ldB;
+        d.nao = m.nao;
+        d.naux = m.naux;
+        d.npair = m.nao * (m.nao + 1) / 2;
+        d.nocc = m.nocc;
+        d.D = m.D;
+        d.C = m.Cocc;
+        d.J = m.J;
+        d.K = m.K;
+        d.vec = (m.ldB % V == 0) && ((reinterpret_cast<uintptr_t>(m.B) & 15) == 0) ? 1 : 0;
+        (void)esz;
+        const int64_t rowblocks = cdiv(d.naux, 8);
+        int64_t chunks = cdiv(64, rowblocks);
+        const int64_t max_chunks = std::max<int64_t>(1, cdiv(d.npair, kT * V * 2));
+        d.j_chunks = std::min(std::max<int64_t>(chunks, 1), max_chunks);
+        d.chunk = cdiv(cdiv(d.npair, d.j_chunks), V) * V;
+        const int64_t colblocks = cdiv(d.npair, kT * V);
+        d.j_splits = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(cdiv(64, colblocks), 1), 64), d.naux);
+        d.prows = cdiv(d.naux, d.j_splits);
+        const int64_t nt = cdiv(d.nao, 128);
+        d.ntl = nt * (nt + 1) / 2;
+        const int64_t nrows = d.naux * d.nocc;
+        int64_t nsplit = std::min<int64_t>(std::max<int64_t>(cdiv(32, d.ntl), 1), cdiv(nrows, 256));
+        nsplit = std::max<int64_t>(nsplit, 1);
+        d.kchunk = cdiv(cdiv(nrows, nsplit), 16) * 16;
+        d.nsplit = cdiv(nrows, d.kchunk);
+        offs.push_back(take(sizeof(double) * d.npair));
+        offs.push_back(take(sizeof(double) * d.naux * d.j_chunks));
+        offs.push_back(take(sizeof(double) * d.naux));
+        offs.push_back(take(sizeof(double) * d.npair * d.j_splits));
+        offs.push_back(take(sizeof(float) * d.nao * d.nocc));
+        offs.push_back(take(sizeof(float) * nrows * d.nao));
+        offs.push_back(take(sizeof(float) * d.nsplit * d.ntl * 128 * 128));
+        b->cost.push_back((double)d.naux * d.nao * d.nao * d.nocc);
+    }
+    int rc;
+    if ((rc = b->work.ensure(total)) || (rc = b->d_mols.ensure(sizeof(MolDesc) * nmol))) {
+        dfjk_batch_destroy(b);
+        return rc;
+    }
+    char* base = static_cast<char*>(b->work.ptr);
+    for (int i = 0; i < nmol; ++i) {
+        MolDesc& d = b->mols[i];
+        const size_t* o = &offs[7 * (size_t)i];
+        d.dt = reinterpret_cast<double*>(base + o[0]);
+        d.rho_part = reinterpret_cast<double*>(base + o[1]);
+        d.rho = reinterpret_cast<double*>(base + o[2]);
+        d.jpart = reinterpret_cast<double*>(base + o[3]);
+        d.Cf = reinterpret_cast<float*>(base + o[4]);
+        d.X = reinterpret_cast<float*>(base + o[5]);
+        d.kpart = reinterpret_cast<float*>(base + o[6]);
+    }
+    b->order.resize(nmol);
+    for (int i = 0; i < nmol; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return b->cost[x] > b->cost[y]; });
+    for (int k = 0; k < kBuckets; ++k) b->tile[k] = pick_tile(16 * (k + 1));
+    if ((rc = build_phases(b))) {
+        dfjk_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return DFJK_OK;
+}
+
+int dfjk_batch_build(dfjk_batch b) {
+    clear_error();
+    if (!b) {
+        set_error("null batch handle");
+        return DFJK_E_INVALID;
+    }
+    return run_all(b, b->stream);
+}
+
+int dfjk_batch_capture(dfjk_batch b) {
+    clear_error();
+    if (!b) {
+        set_error("null batch handle");
+        return DFJK_E_INVALID;
+    }
+    drop_graph(b);
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    DFJK_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    int rc = run_all(b, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        return DFJK_E_HIP;
+    }
+    b->graph = g;
+    DFJK_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return DFJK_OK;
+}
+
+int dfjk_batch_launch(dfjk_batch b) {
+    clear_error();
+    if (!b) {
+        set_error("null batch handle");
+        return DFJK_E_INVALID;
+    }
+    if (!b->exec) {
+        set_error("dfjk_batch_launch: no captured graph (call dfjk_batch_capture)");
+        return DFJK_E_INVALID;
+    }
+    DFJK_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    return DFJK_OK;
+}
+
+int dfjk_batch_get_tile(dfjk_batch b, int bucket, int* tile) {
+    clear_error();
+    if (!b || !tile || bucket < 0 || bucket >= kBuckets) {
+        set_error("dfjk_batch_get_tile: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    *tile = b->tile[bucket];
+    return DFJK_OK;
+}
+
+int dfjk_batch_set_tile(dfjk_batch b, int bucket, int tile) {
+    clear_error();
+    if (!b || bucket < 0 || bucket >= kBuckets || tile < 0 || tile >= k_tile_count()) {
+        set_error("dfjk_batch_set_tile: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    b->tile[bucket] = tile;
+    drop_graph(b);
+    return build_phases(b);
+}
+
+int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* best_ms) {
+    clear_error();
+    if (!b || reps < 1 || reps > 100) {
+        set_error("dfjk_batch_autotune: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    int rc;
+    // cached choices for this dtype
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            int dt, bk, t;
+            double ms;
+            int found = 0;
+            while (fscanf(f, "%d %d %d %lf", &dt, &bk, &t, &ms) == 4)
+                if (dt == b->dtype && bk >= 0 && bk < kBuckets && t >= 0 && t < k_tile_count()) {
+                    b->tile[bk] = t;
+                    if (best_ms) best_ms[bk] = ms;
+                    ++found;
+                }
+            fclose(f);
+            if (found) {
+                drop_graph(b);
+                return build_phases(b);
+            }
+        }
+    }
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    // reference K of every molecule with the current (default) tiles
+    if ((rc = run_all(b, b->stream))) return rc;
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<std::vector<double>> Kref(b->nmol);
+    for (int i = 0; i < b->nmol; ++i) {
+        const MolDesc& d = b->mols[i];
+        Kref[i].resize((size_t)(d.nao * d.nao));
+        DFJK_HIP_TRY(hipMemcpy(Kref[i].data(), d.K, Kref[i].size() * 8, hipMemcpyDeviceToHost));
+    }
+    hipEvent_t e0, e1;
+    DFJK_HIP_TRY(hipEventCreate(&e0));
+    DFJK_HIP_TRY(hipEventCreate(&e1));
+    const int default_tile[kBuckets] = {b->tile[0], b->tile[1], b->tile[2], b->tile[3],
+                                        b->tile[4], b->tile[5], b->tile[6], b->tile[7]};
+    for (int bk = 0; bk < kBuckets; ++bk) {
+        bool present = false;
+        for (const auto& d : b->mols) present |= bucket_of(d.nocc) == bk;
+        if (!present) continue;
+        double best = 1e300;
+        int best_t = b->tile[bk];
+        for (int t = 0; t < k_tile_count(); ++t) {
+            b->tile[bk] = t;
+            if ((rc = build_phases(b))) break;
+            const Phase* ph = nullptr;
+            for (const auto& p : b->phases)
+                if (p.kind < 0 && p.bucket == bk) ph = &p;
+            if (!ph) continue;
+            if ((rc = run_phase(b, *ph, b->stream))) break;  // warm-up
+            double tmin = 1e300;
+            for (int r = 0; r < reps; ++r) {
+                (void)hipEventRecord(e0, b->stream);
+                if ((rc = run_phase(b, *ph, b->stream))) break;
+                (void)hipEventRecord(e1, b->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tmin = std::min(tmin, (double)ms);
+            }
+            if (rc) break;
+            if (tmin < best) {
+                best = tmin;
+                best_t = t;
+            }
+        }
+        if (rc) break;
+        b->tile[bk] = best_t;
+        if (best_ms) best_ms[bk] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    // keep a bucket's choice only if its molecules reproduce the reference K
+    if ((rc = build_phases(b)) || (rc = run_all(b, b->stream))) return rc;
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    bool changed = false;
+    for (int i = 0; i < b->nmol; ++i) {
+        const MolDesc& d = b->mols[i];
+        std::vector<double> K((size_t)(d.nao * d.nao));
+        DFJK_HIP_TRY(hipMemcpy(K.data(), d.K, K.size() * 8, hipMemcpyDeviceToHost));
+        double err = 0, ref = 0;
+        for (size_t e = 0; e < K.size(); ++e) {
+            err = std::max(err, std::fabs(K[e] - Kref[i][e]));
+            ref = std::max(ref, std::fabs(Kref[i][e]));
+        }
+        const int bk = bucket_of(d.nocc);
+        if (err > 1e-5 * ref && b->tile[bk] != default_tile[bk]) {
+            b->tile[bk] = default_tile[bk];
+            changed = true;
+        }
+    }
+    if (changed && (rc = build_phases(b))) return rc;
+    drop_graph(b);
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "w")) {
+            for (int bk = 0; bk < kBuckets; ++bk)
+                fprintf(f, "%d %d %d %.6f\n", b->dtype, bk, b->tile[bk], best_ms ? best_ms[bk] : 0.0);
+            fclose(f);
+        }
+    }
+    return DFJK_OK;
+}
+
+int dfjk_batch_workspace_bytes(dfjk_batch b, size_t* bytes) {
+    clear_error();
+    if (!b || !bytes) {
+        set_error("dfjk_batch_workspace_bytes: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    *bytes = b->work.bytes + b->d_mols.bytes + b->lists.bytes;
+    return DFJK_OK;
+}
+
+void dfjk_batch_destroy(dfjk_batch b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->work.release();
+    b->d_mols.release();
+    b->lists.release();
+    delete b;
+}
+
+}  // extern "C"

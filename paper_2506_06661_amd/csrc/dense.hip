@@ -1,0 +1,337 @@
+// Dense FP64 helpers for the SCF step and the density path of K:
+// a general matrix product on the FP64 matrix cores, deterministic
+// reductions, and a one-workgroup parallel cyclic Jacobi eigensolver.
+#include "dense.h"
+
+#include "mma.h"
+#include "numerics.h"
+
+namespace dfjk {
+
+namespace {
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- GEMM
+// C = alpha * op(A) op(B) + beta * C, row-major, op(X) = X or X^T.
+// 64x64 tile per workgroup, 2x2 waves of 32x32 (2x2 f64 16x16x4 steps).
+constexpr int GT = 64, GK = 16;
+
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, T alpha,
+                                                    const T* __restrict__ A, int64_t lda,
+                                                    const T* __restrict__ B, int64_t ldb, T beta,
+                                                    T* __restrict__ C, int64_t ldc) {
+    __shared__ T sA[GK][GT + 1];  // sA[k][m] = op(A)[m][k]
+    __shared__ T sB[GK][GT + 1];  // sB[k][n] = op(B)[k][n]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.y * GT, n0 = (int64_t)blockIdx.x * GT;
+    typename Mma<T>::acc_t acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = Mma<T>::zero();
+    for (int64_t k0 = 0; k0 < K; k0 += GK) {
+        for (int e = tid; e < GK * GT; e += 256) {
+            // element (k, m) of op(A) and (k, n) of op(B); the mapping reads
+            // memory contiguously
+            int k, m;
+            if (TA) { k = e / GT; m = e % GT; } else { m = e / GK; k = e % GK; }
+            const int64_t gm = m0 + m, gk = k0 + k;
+            T v = T(0);
+            if (gm < M && gk < K) v = TA ? A[gk * lda + gm] : A[gm * lda + gk];
+            sA[k][m] = v;
+            int kb, n;
+            if (TB) { n = e / GK; kb = e % GK; } else { kb = e / GT; n = e % GT; }
+            const int64_t gn = n0 + n, gkb = k0 + kb;
+            T w = T(0);
+            if (gn < N && gkb < K) w = TB ? B[gn * ldb + gkb] : B[gkb * ldb + gn];
+            sB[kb][n] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK / 4; ++kk) {
+            const int kr = kk * 4 + (lane >> 4);
+            T a[2], b[2];
+            for (int q = 0; q < 2; ++q) {
+                a[q] = sA[kr][wm * 32 + q * 16 + (lane & 15)];
+                b[q] = sB[kr][wn * 32 + q * 16 + (lane & 15)];
+            }
+            for (int ti = 0; ti < 2; ++ti)
+                for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
+        }
+        __syncthreads();
+    }
+    for (int ti = 0; ti < 2; ++ti)
+        for (int tj = 0; tj < 2; ++tj)
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm * 32 + ti * 16 + Mma<T>::row(lane, r);
+                const int64_t gn = n0 + wn * 32 + tj * 16 + (lane & 15);
+                if (gm < M && gn < N) {
+                    const T old = beta == T(0) ? T(0) : beta * C[gm * ldc + gn];
+                    C[gm * ldc + gn] = alpha * acc[ti][tj][r] + old;
+                }
+            }
+}
+
+// ---------------------------------------------------------------- reductions
+// part[t * nblk + b] = sum over this block's slice of a_t . b_t
+constexpr int RT = 256, RBLK = 128;
+
+__global__ __launch_bounds__(RT) void dots_partial(DotList list, int64_t n, double* __restrict__ part) {
+    __shared__ double lds[RT / 64];
+    const double* __restrict__ da = list.a[blockIdx.y];
+    const double* __restrict__ db = list.b[blockIdx.y];
+    const int64_t per = cdiv(n, RBLK);
+    const int64_t beg = (int64_t)blockIdx.x * per;
+    const int64_t end = beg + per < n ? beg + per : n;
+    double s = 0.0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += RT) s = fma(da[i], db[i], s);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RT / 64; ++w) t += lds[w];
+        part[blockIdx.y * RBLK + blockIdx.x] = t;
+    }
+}
+
+__global__ void dots_finish(const double* __restrict__ part, int nd, double* __restrict__ out) {
+    const int t = threadIdx.x;
+    if (t >= nd) return;
+    double s = 0.0;
+    for (int b = 0; b < RBLK; ++b) s += part[t * RBLK + b];
+    out[t] = s;
+}
+
+// ---------------------------------------------------------------- Jacobi
+// Parallel cyclic Jacobi on a symmetric n x n matrix A (overwritten; the
+// eigenvalues end on its diagonal), accumulating V (n x n, starts as the
+// caller's basis; columns become eigenvectors in that basis).  Each sweep
+// visits every pair (p,q) once in the round-robin (circle) order: n-1 rounds
+// of n/2 disjoint pairs (a dummy index when n is odd).  Rotations follow the
+// symmetric Schur step of Golub & Van Loan (Matrix Computations, 8.5.2).
+constexpr int JT = 1024;
+
+__device__ inline void pair_of(int r, int k, int m, int& p, int& q) {
+    // circle method on m (even) players; player m-1 fixed
+    if (k == 0) {
+        p = r;
+        q = m - 1;
+    } else {
+        p = (r + k) % (m - 1);
+        q = (r - k + (m - 1)) % (m - 1);
+    }
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+}
+
+__global__ __launch_bounds__(JT) void jacobi_kernel(double* __restrict__ A, double* __restrict__ V,
+                                                     int n, double* __restrict__ cs, int max_sweeps,
+                                                     double tol, int* __restrict__ sweeps_done) {
+    __shared__ double red[JT / 64];
+    __shared__ int stop;
+    const int m = n + (n & 1);
+    const int half = m / 2;
+    double* cc = cs;
+    double* ss = cs + half;
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        // convergence test: off-diagonal norm against the full norm
+        double off = 0.0, all = 0.0;
+        for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += JT) {
+            const double v = A[e];
+            all = fma(v, v, all);
+            if (e / n != e % n) off = fma(v, v, off);
+        }
+        off = wave_sum(off);
+        all = wave_sum(all);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = off;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < JT / 64; ++w) t += red[w];
+            red[0] = t;
+        }
+        __syncthreads();
+        const double off_tot = red[0];
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = all;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < JT / 64; ++w) t += red[w];
+            stop = !(off_tot > tol * tol * t) ? 1 : 0;
+        }
+        __syncthreads();
+        if (stop) break;
+        for (int r = 0; r < m - 1; ++r) {
+            // rotation of each pair from the current A
+            for (int k = threadIdx.x; k < half; k += JT) {
+                int p, q;
+                pair_of(r, k, m, p, q);
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[(int64_t)p * n + q];
+                    if (apq != 0.0) {
+                        const double app = A[(int64_t)p * n + p], aqq = A[(int64_t)q * n + q];
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                cc[k] = c;
+                ss[k] = s;
+            }
+            __syncthreads();
+            // columns: A <- A J, V <- V J
+            for (int64_t e = threadIdx.x; e < (int64_t)half * n; e += JT) {
+                const int k = (int)(e / n), i = (int)(e % n);
+                int p, q;
+                pair_of(r, k, m, p, q);
+                if (q >= n) continue;
+                const double c = cc[k], s = ss[k];
+                const double aip = A[(int64_t)i * n + p], aiq = A[(int64_t)i * n + q];
+                A[(int64_t)i * n + p] = c * aip - s * aiq;
+                A[(int64_t)i * n + q] = s * aip + c * aiq;
+                const double vip = V[(int64_t)i * n + p], viq = V[(int64_t)i * n + q];
+                V[(int64_t)i * n + p] = c * vip - s * viq;
+                V[(int64_t)i * n + q] = s * vip + c * viq;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int64_t e = threadIdx.x; e < (int64_t)half * n; e += JT) {
+                const int k = (int)(e / n), j = (int)(e % n);
+                int p, q;
+                pair_of(r, k, m, p, q);
+                if (q >= n) continue;
+                const double c = cc[k], s = ss[k];
+                const double apj = A[(int64_t)p * n + j], aqj = A[(int64_t)q * n + j];
+                A[(int64_t)p * n + j] = c * apj - s * aqj;
+                A[(int64_t)q * n + j] = s * apj + c * aqj;
+            }
+            __syncthreads();
+            // the rotated pair's off-diagonal element is zero by construction
+            for (int k = threadIdx.x; k < half; k += JT) {
+                int p, q;
+                pair_of(r, k, m, p, q);
+                if (q < n) {
+                    A[(int64_t)p * n + q] = 0.0;
+                    A[(int64_t)q * n + p] = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) *sweeps_done = sweep;
+}
+
+// Ascending order of the diagonal of A (ties by index): rank[i] = position.
+__global__ void eig_rank(const double* __restrict__ A, int n, int* __restrict__ pos_of_rank,
+                         double* __restrict__ w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double ai = A[(int64_t)i * n + i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+        const double aj = A[(int64_t)j * n + j];
+        rank += (aj < ai || (aj == ai && j < i)) ? 1 : 0;
+    }
+    pos_of_rank[rank] = i;
+    w[rank] = ai;
+}
+
+// out[r][c] = scale(c) * V[r][pos_of_rank[c]] for c < ncol (row-major n x ncol)
+__global__ void gather_cols(const double* __restrict__ V, int n, const int* __restrict__ pos_of_rank,
+                            int ncol, const double* __restrict__ w, int mode, double* __restrict__ out,
+                            double* __restrict__ sign) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * ncol) return;
+    const int r = (int)(e / ncol), c = (int)(e % ncol);
+    double f = 1.0;
+    if (mode == 1) f = sqrt(fabs(w[c]));  // signed square-root factor
+    out[e] = f * V[(int64_t)r * n + pos_of_rank[c]];
+    if (sign && r == 0) sign[c] = w[c] < 0.0 ? -1.0 : 1.0;
+}
+
+__global__ void set_identity(double* __restrict__ V, int n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (int64_t)n * n) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+template <typename T>
+int gemm_t(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T alpha, const T* A,
+           int64_t lda, const T* B, int64_t ldb, T beta, T* C, int64_t ldc) {
+    const dim3 grid((unsigned)cdiv(N, GT), (unsigned)cdiv(M, GT));
+    if (!ta && !tb)
+        gemm_kernel<T, false, false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (ta && !tb)
+        gemm_kernel<T, true, false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else if (!ta && tb)
+        gemm_kernel<T, false, true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    else
+        gemm_kernel<T, true, true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    DFJK_LAUNCH_CHECK("gemm_kernel");
+    return DFJK_OK;
+}
+
+int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+          const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+          int64_t ldc) {
+    return gemm_t<double>(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int sgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha,
+          const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+          int64_t ldc) {
+    return gemm_t<float>(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int dots(hipStream_t st, const DotList& list, int nd, int64_t n, double* part, double* out) {
+    if (nd < 1 || nd > kMaxDots) {
+        set_error("dots: %d products outside [1, %d]", nd, kMaxDots);
+        return DFJK_E_INVALID;
+    }
+    dots_partial<<<dim3(RBLK, (unsigned)nd), RT, 0, st>>>(list, n, part);
+    DFJK_LAUNCH_CHECK("dots_partial");
+    dots_finish<<<1, 64, 0, st>>>(part, nd, out);
+    DFJK_LAUNCH_CHECK("dots_finish");
+    return DFJK_OK;
+}
+
+size_t dots_part_elems(int nd) { return (size_t)nd * RBLK; }
+
+int eigh(hipStream_t st, double* A, double* V, int n, bool v_identity, double* work, int* iwork,
+         double* w) {
+    if (n < 1 || n > kMaxEighN) {
+        set_error("eigh: n=%d outside [1, %d]", n, kMaxEighN);
+        return DFJK_E_INVALID;
+    }
+    if (v_identity) {
+        set_identity<<<dim3((unsigned)cdiv((int64_t)n * n, 256)), 256, 0, st>>>(V, n);
+        DFJK_LAUNCH_CHECK("set_identity");
+    }
+    // stop when the off-diagonal norm is below n * eps of the matrix norm
+    const double tol = (double)n * 2.220446049250313e-16;
+    jacobi_kernel<<<1, JT, 0, st>>>(A, V, n, work, 40, tol, iwork);
+    DFJK_LAUNCH_CHECK("jacobi_kernel");
+    eig_rank<<<dim3((unsigned)cdiv(n, 256)), 256, 0, st>>>(A, n, iwork + 1, w);
+    DFJK_LAUNCH_CHECK("eig_rank");
+    return DFJK_OK;
+}
+
+int eig_gather(hipStream_t st, const double* V, int n, const int* iwork, int ncol, const double* w,
+               int mode, double* out, double* sign) {
+    gather_cols<<<dim3((unsigned)cdiv((int64_t)n * ncol, 256)), 256, 0, st>>>(V, n, iwork + 1, ncol, w,
+                                                                               mode, out, sign);
+    DFJK_LAUNCH_CHECK("gather_cols");
+    return DFJK_OK;
+}
+
+}  // namespace dfjk

@@ -85,6 +85,10 @@ struct dfjk_ctx {
 
     int g1_tile = -1;       // GEMM1 tile index (-1: heuristic)
 
+    // SCF state (scf.hip): iterations done, DIIS vectors stored
+    int scf_iter = 0, scf_count = 0;
+    bool scf_ready = false;
+
     dfjk::Prof prof;
 };
 
@@ -98,8 +102,49 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out);
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
                      double* K);
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K);
+int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, int flags,
+             dfjk_scf_info* info);
+int scf_reset(dfjk_ctx* h);
 int k_tile_count();
 int k_tile_info(int t, int* ni, int* wm);
+
+// Batched builds (batch.hip drives; j_kernels.hip / k_kernels.hip launch).
+// One descriptor per molecule; all pointers are device pointers.
+struct MolDesc {
+    const void* B;
+    int64_t ldB, nao, naux, npair, nocc;
+    const double* D;
+    const double* C;
+    double* J;
+    double* K;
+    double* dt;        // npair
+    double* rho_part;  // naux x j_chunks
+    double* rho;       // naux
+    double* jpart;     // j_splits x npair
+    float* Cf;         // nao x nocc
+    float* X;          // naux*nocc x nao
+    float* kpart;      // nsplit x ntl x 128 x 128
+    int64_t j_chunks, j_splits, chunk, prows;
+    int64_t nsplit, kchunk, ntl;
+    int64_t g1_nib, g1_nmb;
+    int vec;
+};
+
+// A phase launch over a subset of molecules: ids (device, n entries, in
+// dispatch order) and prefix (device, n+1 entries) of per-molecule block counts.
+struct PhaseList {
+    const int* ids;
+    const int64_t* prefix;
+    int n;
+    int64_t nblk;
+};
+
+enum BatchPhaseKind { BP_PACK = 0, BP_RHO, BP_RHO_FIN, BP_OUT, BP_JFIN, BP_CF32, BP_SYRK, BP_KFIN, BP_NKIND };
+int j_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl);
+int k_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl);
+int k_batch_gemm1(hipStream_t st, int dtype, int tile, const MolDesc* mols, const PhaseList& pl);
+int pick_tile(int64_t ncol);
+int tile_nb(int tile, int64_t nao, int64_t ncol, int64_t* nib, int64_t* nmb);
 
 // quantisation (quantize.hip)
 int quantize(const double* src, void* dst, int dtype, int64_t n, hipStream_t s);

@@ -28,14 +28,18 @@ constexpr int kOutVec = 2;      // double2 loads per row per thread in pass 2
 constexpr int kOutCols = kThreads * 2 * kOutVec;  // columns per workgroup in pass 2
 
 // dt[p(mu,nu)] for all mu <= nu; one block per row nu of the packed triangle.
-__global__ __launch_bounds__(kThreads) void pack_density(const double* __restrict__ D, int64_t nao,
-                                                          double* __restrict__ dt) {
-    const int64_t nu = blockIdx.x;
+__device__ inline void pack_density_body(int64_t nu, const double* __restrict__ D, int64_t nao,
+                                         double* __restrict__ dt) {
     const int64_t base = nu * (nu + 1) / 2;
     for (int64_t mu = threadIdx.x; mu <= nu; mu += kThreads) {
         const double v = (mu == nu) ? D[nu * nao + nu] : D[mu * nao + nu] + D[nu * nao + mu];
         dt[base + mu] = v;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void pack_density(const double* __restrict__ D, int64_t nao,
+                                                          double* __restrict__ dt) {
+    pack_density_body(blockIdx.x, D, nao, dt);
 }
 
 // Sum of `v` over the 256 threads of the block; result valid in thread 0.
@@ -102,14 +106,19 @@ __global__ __launch_bounds__(kThreads) void j_rho_f64(const double* __restrict__
     }
 }
 
-__global__ void j_rho_finish(const double* __restrict__ part, int64_t naux, int nchunk,
-                             double* __restrict__ rho, double* __restrict__ rho_out) {
-    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void rho_finish_body(int64_t P, const double* __restrict__ part, int64_t naux,
+                                       int nchunk, double* __restrict__ rho,
+                                       double* __restrict__ rho_out) {
     if (P >= naux) return;
     double s = 0.0;
     for (int c = 0; c < nchunk; ++c) s += part[P * nchunk + c];
     rho[P] = s;
     if (rho_out) rho_out[P] = s;
+}
+
+__global__ void j_rho_finish(const double* __restrict__ part, int64_t naux, int nchunk,
+                             double* __restrict__ rho, double* __restrict__ rho_out) {
+    rho_finish_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, part, naux, nchunk, rho, rho_out);
 }
 
 template <bool VEC>
@@ -165,9 +174,8 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
 }
 
 // J[nu,mu] = J[mu,nu] = sum_s jpart[s][p(mu,nu)]; one block per packed row nu.
-__global__ __launch_bounds__(kThreads) void j_finish(const double* __restrict__ jpart, int64_t npair,
-                                                      int nsplit, int64_t nao, double* __restrict__ J) {
-    const int64_t nu = blockIdx.x;
+__device__ inline void j_finish_body(int64_t nu, const double* __restrict__ jpart, int64_t npair,
+                                     int nsplit, int64_t nao, double* __restrict__ J) {
     const int64_t base = nu * (nu + 1) / 2;
     for (int64_t mu = threadIdx.x; mu <= nu; mu += kThreads) {
         double v = 0.0;
@@ -175,6 +183,11 @@ __global__ __launch_bounds__(kThreads) void j_finish(const double* __restrict__ 
         J[nu * nao + mu] = v;
         J[mu * nao + nu] = v;
     }
+}
+
+__global__ __launch_bounds__(kThreads) void j_finish(const double* __restrict__ jpart, int64_t npair,
+                                                      int nsplit, int64_t nao, double* __restrict__ J) {
+    j_finish_body(blockIdx.x, jpart, npair, nsplit, nao, J);
 }
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -249,15 +262,13 @@ __global__ void split_f64(const double* __restrict__ x, int64_t n, float* __rest
 }
 
 template <typename TB, int R, int ACC>
-__global__ __launch_bounds__(kThreads) void j_rho_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
-                                                       int64_t npair, const double* __restrict__ dt,
-                                                       const float* __restrict__ dhi,
-                                                       const float* __restrict__ dlo, int64_t chunk,
-                                                       int nchunk, bool vec, double* __restrict__ part) {
+__device__ inline void j_rho_red_body(int64_t bx, int c, const TB* __restrict__ B, int64_t ldB,
+                                      int64_t naux, int64_t npair, const double* __restrict__ dt,
+                                      const float* __restrict__ dhi, const float* __restrict__ dlo,
+                                      int64_t chunk, int nchunk, bool vec, double* __restrict__ part) {
     constexpr int V = Elem<TB>::V;
     __shared__ double lds[4];
-    const int64_t P0 = (int64_t)blockIdx.x * R;
-    const int c = blockIdx.y;
+    const int64_t P0 = bx * R;
     const int64_t c0 = (int64_t)c * chunk;
     const int64_t c1 = c0 + chunk < npair ? c0 + chunk : npair;
     const TB* rows[R];
@@ -305,17 +316,25 @@ __global__ __launch_bounds__(kThreads) void j_rho_red(const TB* __restrict__ B, 
     }
 }
 
+template <typename TB, int R, int ACC>
+__global__ __launch_bounds__(kThreads) void j_rho_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
+                                                       int64_t npair, const double* __restrict__ dt,
+                                                       const float* __restrict__ dhi,
+                                                       const float* __restrict__ dlo, int64_t chunk,
+                                                       int nchunk, bool vec, double* __restrict__ part) {
+    j_rho_red_body<TB, R, ACC>(blockIdx.x, blockIdx.y, B, ldB, naux, npair, dt, dhi, dlo, chunk, nchunk,
+                               vec, part);
+}
+
 template <typename TB, int ACC>
-__global__ __launch_bounds__(kThreads) void j_out_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
-                                                       int64_t npair, const double* __restrict__ rho,
-                                                       const float* __restrict__ rhi,
-                                                       const float* __restrict__ rlo, int64_t prows,
-                                                       bool vec, double* __restrict__ jpart) {
+__device__ inline void j_out_red_body(int64_t bx, int s, const TB* __restrict__ B, int64_t ldB,
+                                      int64_t naux, int64_t npair, const double* __restrict__ rho,
+                                      const float* __restrict__ rhi, const float* __restrict__ rlo,
+                                      int64_t prows, bool vec, double* __restrict__ jpart) {
     constexpr int V = Elem<TB>::V;
-    const int s = blockIdx.y;
     const int64_t P0 = (int64_t)s * prows;
     const int64_t P1 = P0 + prows < naux ? P0 + prows : naux;
-    const int64_t col0 = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * V;
+    const int64_t col0 = (bx * kThreads + threadIdx.x) * V;
     Acc<ACC> acc[V];
     if (vec && col0 + V <= npair) {
 #pragma unroll 4
@@ -342,6 +361,15 @@ __global__ __launch_bounds__(kThreads) void j_out_red(const TB* __restrict__ B, 
 #pragma unroll
     for (int v = 0; v < V; ++v)
         if (col0 + v < npair) out[col0 + v] = acc[v].value();
+}
+
+template <typename TB, int ACC>
+__global__ __launch_bounds__(kThreads) void j_out_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
+                                                       int64_t npair, const double* __restrict__ rho,
+                                                       const float* __restrict__ rhi,
+                                                       const float* __restrict__ rlo, int64_t prows,
+                                                       bool vec, double* __restrict__ jpart) {
+    j_out_red_body<TB, ACC>(blockIdx.x, blockIdx.y, B, ldB, naux, npair, rho, rhi, rlo, prows, vec, jpart);
 }
 
 template <typename TB, int ACC>
@@ -400,7 +428,70 @@ int j_build_red(dfjk_ctx* h, double* J, double* rho_out) {
     }
 }
 
+// ---------------------------------------------------------------- batched
+__device__ inline int find_mol(const int64_t* __restrict__ prefix, int n, int64_t b) {
+    int lo = 0, hi = n - 1;  // largest j with prefix[j] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kBatchR = 8;
+
+template <typename TB>
+__global__ __launch_bounds__(kThreads) void jb_kernel(int kind, const MolDesc* __restrict__ mols,
+                                                       PhaseList pl) {
+    const int64_t b = blockIdx.x;
+    const int j = find_mol(pl.prefix, pl.n, b);
+    const MolDesc& d = mols[pl.ids[j]];
+    const int64_t lid = b - pl.prefix[j];
+    const TB* B = static_cast<const TB*>(d.B);
+    switch (kind) {
+        case BP_PACK:
+            pack_density_body(lid, d.D, d.nao, d.dt);
+            break;
+        case BP_RHO: {
+            const int64_t nrb = cdiv(d.naux, kBatchR);
+            j_rho_red_body<TB, kBatchR, ACC_F64>(lid % nrb, (int)(lid / nrb), B, d.ldB, d.naux, d.npair,
+                                                 d.dt, nullptr, nullptr, d.chunk, (int)d.j_chunks,
+                                                 d.vec != 0, d.rho_part);
+            break;
+        }
+        case BP_RHO_FIN:
+            rho_finish_body(lid * kThreads + threadIdx.x, d.rho_part, d.naux, (int)d.j_chunks, d.rho,
+                            nullptr);
+            break;
+        case BP_OUT: {
+            const int64_t ncb = cdiv(d.npair, (int64_t)kThreads * Elem<TB>::V);
+            j_out_red_body<TB, ACC_F64>(lid % ncb, (int)(lid / ncb), B, d.ldB, d.naux, d.npair, d.rho,
+                                        nullptr, nullptr, d.prows, d.vec != 0, d.jpart);
+            break;
+        }
+        case BP_JFIN:
+            j_finish_body(lid, d.jpart, d.npair, (int)d.j_splits, d.nao, d.J);
+            break;
+        default:
+            break;
+    }
+}
+
 }  // namespace
+
+int j_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl) {
+    if (pl.nblk <= 0) return DFJK_OK;
+    const dim3 grid((unsigned)pl.nblk);
+    switch (dtype) {
+        case DFJK_F32: jb_kernel<float><<<grid, kThreads, 0, st>>>(kind, mols, pl); break;
+        case DFJK_BF16: jb_kernel<uint16_t><<<grid, kThreads, 0, st>>>(kind, mols, pl); break;
+        case DFJK_F16: jb_kernel<_Float16><<<grid, kThreads, 0, st>>>(kind, mols, pl); break;
+        default: set_error("batched builds take FP32, BF16 or FP16 B"); return DFJK_E_DTYPE;
+    }
+    DFJK_LAUNCH_CHECK("jb_kernel");
+    return DFJK_OK;
+}
 
 int j_setup(dfjk_ctx* h) {
     const int64_t rowblocks = cdiv(h->naux, kRhoRows);

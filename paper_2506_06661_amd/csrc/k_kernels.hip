@@ -17,37 +17,11 @@
 // own partial tile, and a last kernel adds the splits in a fixed order and
 // mirrors the result, so K is bitwise reproducible.
 #include "internal.h"
+#include "mma.h"
 
 namespace dfjk {
 
 namespace {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-// One 16x16x4 matrix-core step per element type.  Operands: lane l supplies
-// A[l%16][l/16] and B[l/16][l%16].  Result element r of lane l is row
-// row(l, r), column l%16 (measured: the FP64 and FP32 instructions differ).
-template <typename T>
-struct Mma;
-template <>
-struct Mma<double> {
-    typedef v4d acc_t;
-    __device__ static acc_t zero() { return v4d{0.0, 0.0, 0.0, 0.0}; }
-    __device__ static acc_t step(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
-};
-template <>
-struct Mma<float> {
-    typedef v4f acc_t;
-    __device__ static acc_t zero() { return v4f{0.f, 0.f, 0.f, 0.f}; }
-    __device__ static acc_t step(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
 
 constexpr int kThreads = 256;
 constexpr int KC = 16;      // contraction chunk held in LDS
@@ -200,15 +174,13 @@ __device__ inline int64_t xcd_logical(int64_t hw, int64_t nblk) {
 // X[(P*ncol + i)*ldx + mu] = sum_nu C[nu][i] B_P[nu][mu]
 // 1-D grid of nib * nmb * naux blocks; logical id -> (i block fastest, mu block, P)
 template <typename T, typename TS, int NI, int WM>
-__global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
-                                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
-                                                     T* __restrict__ X, int64_t ldx, int64_t nib,
-                                                     int64_t nmb, int64_t nblk) {
+__device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
+                                    const T* __restrict__ C, int64_t ldc, int64_t ncol,
+                                    T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb) {
     constexpr int BI = 16 * NI, BM = 64 * WM;
     __shared__ T sC[2][KC][BI + 1];
     __shared__ T sB[2][KC][BM + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t lid = xcd_logical(blockIdx.x, nblk);
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, mu0 = mb * BM;
     const TS* Bp = B + P * ldB;
@@ -262,6 +234,15 @@ __global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, in
             }
 }
 
+template <typename T, typename TS, int NI, int WM>
+__global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
+                                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
+                                                     T* __restrict__ X, int64_t ldx, int64_t nib,
+                                                     int64_t nmb, int64_t nblk) {
+    k_gemm1_body<T, TS, NI, WM>(xcd_logical(blockIdx.x, nblk), B, ldB, nao, C, ldc, ncol, X, ldx, nib,
+                                nmb);
+}
+
 // ---------------------------------------------------------------- GEMM2 (SYRK)
 template <typename T>
 struct SyStage {
@@ -288,16 +269,13 @@ __device__ inline void sy_load(SyStage<T>& st, const T* __restrict__ X, int64_t 
 // partial[(s*ntl + t)][m][n] = sum_{k in split s} X[k][mu0+m] * sign_k * X[k][nu0+n]
 // grid: x = lower tile t (I >= J), y = split s
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int64_t ldx, int64_t nrows,
-                                                    int64_t nao, int64_t ncol,
-                                                    const double* __restrict__ sign, int64_t kchunk,
-                                                    int64_t ntl, int64_t nblk, T* __restrict__ part) {
+__device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t ldx, int64_t nrows,
+                                   int64_t nao, int64_t ncol, const double* __restrict__ sign,
+                                   int64_t kchunk, int64_t ntl, T* __restrict__ part) {
     __shared__ T sA[2][KC][SY_T + 1];
     __shared__ T sB[2][KC][SY_T + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    // all tiles of one split run on one XCD and share its L2 copy of the X rows
-    const int64_t lid = xcd_logical(blockIdx.x, nblk);
     const int64_t t = lid % ntl;
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
@@ -365,13 +343,21 @@ __global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int6
             }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int64_t ldx, int64_t nrows,
+                                                    int64_t nao, int64_t ncol,
+                                                    const double* __restrict__ sign, int64_t kchunk,
+                                                    int64_t ntl, int64_t nblk, T* __restrict__ part) {
+    // all tiles of one split run on one XCD and share its L2 copy of the X rows
+    k_syrk_body<T>(xcd_logical(blockIdx.x, nblk), X, ldx, nrows, nao, ncol, sign, kchunk, ntl, part);
+}
+
 // K[mu][nu] = K[nu][mu] = scale * sum_s partial[s][t][m][n] over the lower
 // triangle (on diagonal tiles only m >= n is used, so K is exactly symmetric).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ part,
-                                                           int64_t nsplit, int64_t ntl, int64_t nao,
-                                                           double scale, double* __restrict__ K) {
-    const int64_t t = blockIdx.x;
+__device__ inline void k_syrk_finish_body(int64_t t, const T* __restrict__ part, int64_t nsplit,
+                                          int64_t ntl, int64_t nao, double scale,
+                                          double* __restrict__ K) {
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -387,6 +373,13 @@ __global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ 
         K[mu * nao + nu] = v;
         K[nu * nao + mu] = v;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ part, int64_t nsplit,
+                                                           int64_t ntl, int64_t nao, double scale,
+                                                           double* __restrict__ K) {
+    k_syrk_finish_body<T>(blockIdx.x, part, nsplit, ntl, nao, scale, K);
 }
 
 template <typename T, typename TS, int NI, int WM>
@@ -486,7 +479,98 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
     return DFJK_OK;
 }
 
+// ---------------------------------------------------------------- batched
+__device__ inline int find_mol_k(const int64_t* __restrict__ prefix, int n, int64_t b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void kb_kernel(int kind, const MolDesc* __restrict__ mols,
+                                                       PhaseList pl) {
+    // SYRK blocks are renumbered so runs of consecutive ids share an XCD
+    const int64_t b = kind == BP_SYRK ? xcd_logical(blockIdx.x, pl.nblk) : (int64_t)blockIdx.x;
+    const int j = find_mol_k(pl.prefix, pl.n, b);
+    const MolDesc& d = mols[pl.ids[j]];
+    const int64_t lid = b - pl.prefix[j];
+    switch (kind) {
+        case BP_CF32: {
+            const int64_t e = lid * kThreads + threadIdx.x;
+            if (e < d.nao * d.nocc) d.Cf[e] = (float)d.C[e];
+            break;
+        }
+        case BP_SYRK:
+            k_syrk_body<float>(lid, d.X, d.nao, d.naux * d.nocc, d.nao, d.nocc, nullptr, d.kchunk, d.ntl,
+                               d.kpart);
+            break;
+        case BP_KFIN:
+            k_syrk_finish_body<float>(lid, d.kpart, d.nsplit, d.ntl, d.nao, 2.0, d.K);
+            break;
+        default:
+            break;
+    }
+}
+
+template <typename TS, int NI, int WM>
+__global__ __launch_bounds__(kThreads) void kb_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
+    const int64_t b = xcd_logical(blockIdx.x, pl.nblk);
+    const int j = find_mol_k(pl.prefix, pl.n, b);
+    const MolDesc& d = mols[pl.ids[j]];
+    k_gemm1_body<float, TS, NI, WM>(b - pl.prefix[j], static_cast<const TS*>(d.B), d.ldB, d.nao, d.Cf,
+                                     d.nocc, d.nocc, d.X, d.nao, d.g1_nib, d.g1_nmb);
+}
+
+template <int NI, int WM>
+int launch_kb_gemm1(hipStream_t st, int dtype, const MolDesc* mols, const PhaseList& pl) {
+    const dim3 grid((unsigned)pl.nblk);
+    switch (dtype) {
+        case DFJK_F32: kb_gemm1<float, NI, WM><<<grid, kThreads, 0, st>>>(mols, pl); break;
+        case DFJK_BF16: kb_gemm1<uint16_t, NI, WM><<<grid, kThreads, 0, st>>>(mols, pl); break;
+        case DFJK_F16: kb_gemm1<_Float16, NI, WM><<<grid, kThreads, 0, st>>>(mols, pl); break;
+        default: set_error("batched builds take FP32, BF16 or FP16 B"); return DFJK_E_DTYPE;
+    }
+    DFJK_LAUNCH_CHECK("kb_gemm1");
+    return DFJK_OK;
+}
+
+typedef int (*KbLaunch)(hipStream_t, int, const MolDesc*, const PhaseList&);
+#define KBT(a, b) launch_kb_gemm1<a, b>
+const KbLaunch kKbTiles[] = {KBT(1, 2), KBT(2, 2), KBT(3, 2), KBT(4, 2), KBT(5, 2), KBT(6, 2),
+                             KBT(7, 2), KBT(8, 2), KBT(13, 1), KBT(4, 4), KBT(7, 1), KBT(5, 1)};
+#undef KBT
+static_assert(sizeof(kKbTiles) / sizeof(kKbTiles[0]) == kNumG1Tiles, "tile tables differ");
+
 }  // namespace
+
+int k_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl) {
+    (void)dtype;
+    if (pl.nblk <= 0) return DFJK_OK;
+    kb_kernel<<<dim3((unsigned)pl.nblk), kThreads, 0, st>>>(kind, mols, pl);
+    DFJK_LAUNCH_CHECK("kb_kernel");
+    return DFJK_OK;
+}
+
+int k_batch_gemm1(hipStream_t st, int dtype, int tile, const MolDesc* mols, const PhaseList& pl) {
+    if (pl.nblk <= 0) return DFJK_OK;
+    if (tile < 0 || tile >= kNumG1Tiles) {
+        set_error("tile %d out of range", tile);
+        return DFJK_E_INVALID;
+    }
+    return kKbTiles[tile](st, dtype, mols, pl);
+}
+
+int pick_tile(int64_t ncol) { return pick_g1_tile(ncol); }
+
+int tile_nb(int tile, int64_t nao, int64_t ncol, int64_t* nib, int64_t* nmb) {
+    if (tile < 0 || tile >= kNumG1Tiles) return DFJK_E_INVALID;
+    *nib = cdiv(ncol, 16 * kG1Tiles[tile].ni);
+    *nmb = cdiv(nao, 64 * kG1Tiles[tile].wm);
+    return DFJK_OK;
+}
 
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
                      double* K) {
@@ -501,12 +585,6 @@ int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* s
     }
 }
 
-int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
-    (void)D;
-    (void)K;
-    set_error("K from a density matrix is not built yet (pass Cocc)");
-    return DFJK_E_INVALID;
-}
 
 int k_tile_count() { return kNumG1Tiles; }
 

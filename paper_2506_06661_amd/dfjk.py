@@ -29,6 +29,21 @@ class DFJKError(RuntimeError):
         self.code = code
 
 
+class ScfInfo(ctypes.Structure):
+    _fields_ = [("e_tot", ctypes.c_double), ("e_1e", ctypes.c_double), ("e_j", ctypes.c_double),
+                ("e_k", ctypes.c_double), ("err_norm", ctypes.c_double), ("d_e", ctypes.c_double),
+                ("iter", ctypes.c_int), ("converged", ctypes.c_int)]
+
+
+DFJK_SCF_C_VALID = 1
+
+
+class Mol(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_void_p), ("nao", ctypes.c_int64), ("naux", ctypes.c_int64),
+                ("ldB", ctypes.c_int64), ("nocc", ctypes.c_int64), ("D", ctypes.c_void_p),
+                ("Cocc", ctypes.c_void_p), ("J", ctypes.c_void_p), ("K", ctypes.c_void_p)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("diis_space", ctypes.c_int), ("conv_tol", ctypes.c_double),
                 ("conv_tol_grad", ctypes.c_double), ("max_cycle", ctypes.c_int),
@@ -57,12 +72,43 @@ def lib():
         L.dfjk_default_options.argtypes = [ctypes.POINTER(Options)]
         L.dfjk_default_options.restype = None
         L.dfjk_quantize.argtypes = [vp, vp, i32, i64, vp]
+        L.dfjk_batch_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Mol), i32, i32, vp]
+        for name in ("dfjk_batch_build", "dfjk_batch_capture", "dfjk_batch_launch"):
+            getattr(L, name).argtypes = [vp]
+        L.dfjk_batch_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(dbl)]
+        L.dfjk_batch_get_tile.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.dfjk_batch_set_tile.argtypes = [vp, i32, i32]
+        L.dfjk_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.dfjk_batch_destroy.argtypes = [vp]
+        L.dfjk_batch_destroy.restype = None
+        for name in ("dfjk_batch_init", "dfjk_batch_build", "dfjk_batch_capture", "dfjk_batch_launch",
+                     "dfjk_batch_autotune", "dfjk_batch_get_tile", "dfjk_batch_set_tile",
+                     "dfjk_batch_workspace_bytes"):
+            getattr(L, name).restype = i32
+        L.dfjk_mlp_init.argtypes = [ctypes.POINTER(vp), i32, i32, i64, vp]
+        L.dfjk_mlp_nparam.argtypes = [vp]
+        L.dfjk_mlp_nparam.restype = i64
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.dfjk_mlp_set_params.argtypes = [vp, fp]
+        L.dfjk_mlp_get.argtypes = [vp, i32, fp]
+        L.dfjk_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.dfjk_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp]
+        L.dfjk_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        L.dfjk_mlp_destroy.argtypes = [vp]
+        L.dfjk_mlp_destroy.restype = None
+        L.dfjk_guess_features.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.dfjk_guess_assemble.argtypes = [vp, vp, i64, vp, vp]
+        for name in ("dfjk_mlp_init", "dfjk_mlp_set_params", "dfjk_mlp_get", "dfjk_mlp_forward",
+                     "dfjk_mlp_loss_grad", "dfjk_mlp_adam", "dfjk_guess_features", "dfjk_guess_assemble"):
+            getattr(L, name).restype = i32
+        L.dfjk_scf_step.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.POINTER(ScfInfo)]
+        L.dfjk_scf_reset.argtypes = [vp]
         L.dfjk_tile_count.argtypes = [i32]
         L.dfjk_tile_info.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.dfjk_set_tile.argtypes = [vp, i32, i32]
         L.dfjk_profile.argtypes = [vp, i32]
         L.dfjk_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]
-        for name in ("dfjk_tile_count", "dfjk_tile_info", "dfjk_set_tile", "dfjk_profile", "dfjk_profile_read", "dfjk_init", "dfjk_build_J", "dfjk_build_K", "dfjk_build_K_factored",
+        for name in ("dfjk_scf_step", "dfjk_scf_reset", "dfjk_tile_count", "dfjk_tile_info", "dfjk_set_tile", "dfjk_profile", "dfjk_profile_read", "dfjk_init", "dfjk_build_J", "dfjk_build_K", "dfjk_build_K_factored",
                      "dfjk_workspace_bytes", "dfjk_quantize"):
             getattr(L, name).restype = i32
         _lib = L
@@ -132,6 +178,18 @@ def dfjk_workspace_bytes(h) -> int:
 DFJK_TILE_GEMM1 = 0
 
 
+def dfjk_scf_step(h, H, D, Cocc, nocc: int, flags: int = 0, want_info: bool = True):
+    """One SCF iteration; returns (rc, ScfInfo or None)."""
+    info = ScfInfo() if want_info else None
+    rc = lib().dfjk_scf_step(h, _ptr(H), _ptr(D), _ptr(Cocc), nocc, flags,
+                             ctypes.byref(info) if want_info else None)
+    return _check("dfjk_scf_step", rc), info
+
+
+def dfjk_scf_reset(h) -> int:
+    return _check("dfjk_scf_reset", lib().dfjk_scf_reset(h))
+
+
 def dfjk_tile_count(kernel: int = DFJK_TILE_GEMM1) -> int:
     return _check("dfjk_tile_count", lib().dfjk_tile_count(kernel))
 
@@ -144,6 +202,134 @@ def dfjk_tile_info(kernel: int, index: int):
 
 def dfjk_set_tile(h, kernel: int, index: int) -> int:
     return _check("dfjk_set_tile", lib().dfjk_set_tile(h, kernel, index))
+
+
+class Batch:
+    """Batched J/K over molecules given as dicts with device tensors
+    B (naux x ldB), D, J, K (nao x nao FP64), C (nao x nocc FP64)."""
+
+    def __init__(self, mols, dtype: int, stream=None):
+        self.mols = mols  # keep the tensors alive
+        arr = (Mol * len(mols))()
+        for i, m in enumerate(mols):
+            B = m["B"]
+            arr[i] = Mol(_ptr(B), m["nao"], B.shape[0], B.shape[1], m["C"].shape[1], _ptr(m["D"]),
+                         _ptr(m["C"]), _ptr(m["J"]), _ptr(m["K"]))
+        self.h = ctypes.c_void_p()
+        _check("dfjk_batch_init", lib().dfjk_batch_init(ctypes.byref(self.h), arr, len(mols), dtype,
+                                                         _stream(stream)))
+
+    def build(self):
+        return _check("dfjk_batch_build", lib().dfjk_batch_build(self.h))
+
+    def capture(self):
+        return _check("dfjk_batch_capture", lib().dfjk_batch_capture(self.h))
+
+    def launch(self):
+        return _check("dfjk_batch_launch", lib().dfjk_batch_launch(self.h))
+
+    def autotune(self, reps: int = 3, cache_path: str | None = None):
+        ms = (ctypes.c_double * 8)()
+        _check("dfjk_batch_autotune", lib().dfjk_batch_autotune(
+            self.h, reps, cache_path.encode() if cache_path else None, ms))
+        return list(ms)
+
+    def tile(self, bucket: int) -> int:
+        t = ctypes.c_int()
+        _check("dfjk_batch_get_tile", lib().dfjk_batch_get_tile(self.h, bucket, ctypes.byref(t)))
+        return t.value
+
+    def set_tile(self, bucket: int, tile: int):
+        return _check("dfjk_batch_set_tile", lib().dfjk_batch_set_tile(self.h, bucket, tile))
+
+    def workspace_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check("dfjk_batch_workspace_bytes", lib().dfjk_batch_workspace_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if self.h:
+            lib().dfjk_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """The learned-guess perceptron on the GPU (parameters live in the library)."""
+
+    def __init__(self, d_in: int = 8, hidden: int = 256, max_batch: int = 65536, stream=None):
+        import numpy as np
+        self._np = np
+        self.d_in, self.hidden = d_in, hidden
+        self.h = ctypes.c_void_p()
+        _check("dfjk_mlp_init", lib().dfjk_mlp_init(ctypes.byref(self.h), d_in, hidden, max_batch,
+                                                     _stream(stream)))
+        self.nparam = int(lib().dfjk_mlp_nparam(self.h))
+
+    def shapes(self):
+        H, d = self.hidden, self.d_in
+        return [(H, d), (H,), (H, H), (H,), (1, H), (1,)]
+
+    def set_params(self, flat):
+        a = self._np.ascontiguousarray(flat, dtype=self._np.float32)
+        assert a.size == self.nparam
+        _check("dfjk_mlp_set_params", lib().dfjk_mlp_set_params(
+            self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def _get(self, which):
+        a = self._np.empty(self.nparam, dtype=self._np.float32)
+        _check("dfjk_mlp_get", lib().dfjk_mlp_get(self.h, which, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a
+
+    def params(self):
+        return self._get(0)
+
+    def grads(self):
+        return self._get(1)
+
+    def unflatten(self, flat):
+        out, o = [], 0
+        for s in self.shapes():
+            n = int(self._np.prod(s))
+            out.append(flat[o:o + n].reshape(s))
+            o += n
+        return out
+
+    def forward(self, X, y):
+        return _check("dfjk_mlp_forward", lib().dfjk_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(y)))
+
+    def loss_grad(self, X, t, loss=None):
+        return _check("dfjk_mlp_loss_grad", lib().dfjk_mlp_loss_grad(self.h, _ptr(X), _ptr(t), X.shape[0],
+                                                                      _ptr(loss)))
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        return _check("dfjk_mlp_adam", lib().dfjk_mlp_adam(self.h, lr, b1, b2, eps))
+
+    def close(self):
+        if self.h:
+            lib().dfjk_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dfjk_guess_features(H, Dcore, R, nao, X, stream=None):
+    return _check("dfjk_guess_features", lib().dfjk_guess_features(_ptr(H), _ptr(Dcore), _ptr(R), nao,
+                                                                    _ptr(X), _stream(stream)))
+
+
+def dfjk_guess_assemble(y, Dcore, nao, D, stream=None):
+    return _check("dfjk_guess_assemble", lib().dfjk_guess_assemble(_ptr(y), _ptr(Dcore), nao, _ptr(D),
+                                                                    _stream(stream)))
 
 
 PHASES = ("J", "J_rho", "J_out", "K", "K_gemm1", "K_syrk", "K_finish")

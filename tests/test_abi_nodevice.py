@@ -60,3 +60,26 @@ def test_no_device_reported():
     h = ctypes.c_void_p()
     assert L.dfjk_init(ctypes.byref(h), ctypes.c_void_p(4096), 0, 4, 4, 10, None, None) == -2
     assert "no HIP device" in pkg.dfjk_last_error()
+
+
+def test_batch_invalid_arguments(L):
+    import paper_2506_06661_amd as pkg
+    from paper_2506_06661_amd.dfjk import Mol
+    b = ctypes.c_void_p()
+    arr = (Mol * 1)()
+    arr[0] = Mol(4096, 4, 8, 10, 2, 4096, 4096, 4096, 4096)
+    assert L.dfjk_batch_init(None, arr, 1, 1, None) == -1
+    assert L.dfjk_batch_init(ctypes.byref(b), arr, 0, 1, None) == -1
+    assert L.dfjk_batch_init(ctypes.byref(b), arr, 1, 0, None) == -5  # FP64 is not batched
+    arr[0] = Mol(4096, 4, 8, 9, 2, 4096, 4096, 4096, 4096)              # ldB < npair
+    assert L.dfjk_batch_init(ctypes.byref(b), arr, 1, 1, None) == -1
+    assert "molecule 0" in pkg.dfjk_last_error()
+    assert L.dfjk_batch_build(None) == -1
+    assert L.dfjk_batch_launch(None) == -1
+    L.dfjk_batch_destroy(None)
+
+
+def test_scf_invalid_arguments(L):
+    fake = ctypes.c_void_p(4096)
+    assert L.dfjk_scf_step(None, fake, fake, fake, 2, 0, None) == -1
+    assert L.dfjk_scf_reset(None) == -1
