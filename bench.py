@@ -82,12 +82,259 @@ def counter_traffic(workload: str):
     return info["traffic_bytes"]
 
 
+def time_steps(pkg, h, Dd, Cd, cfg, steps, warmup):
+    """Per-phase event averages over `steps` J+K steps on handle h."""
+    import torch
+
+    J = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+    K = torch.empty_like(J)
+    for _ in range(warmup):
+        pkg.dfjk_build_J(h.h, Dd, J)
+        pkg.dfjk_build_K(h.h, Cd, cfg.nocc, None, K)
+    torch.cuda.synchronize()
+    pkg.dfjk_profile(h.h, max(steps, 1))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        pkg.dfjk_build_J(h.h, Dd, J)
+        pkg.dfjk_build_K(h.h, Cd, cfg.nocc, None, K)
+    e1.record()
+    torch.cuda.synchronize()
+    prof = pkg.dfjk_profile_read(h.h)
+    pkg.dfjk_profile(h.h, 0)
+    return {"ms_per_step": e0.elapsed_time(e1) / steps,
+            "phase_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()}}
+
+
+def bench_c3(args):
+    """nao=2048, naux=8192, nocc=400: B stored in BF16 and in FP16 (34 GB each),
+    generated in FP64 row blocks on the host and rounded on the device."""
+    import torch
+
+    import paper_2506_06661_amd as pkg
+    import synth
+
+    cfg = synth.C3
+    R = synth.positions(cfg)
+    C = synth.C_occ(cfg.seed, cfg.nao, cfg.nocc)
+    D = 2.0 * C @ C.T
+    Cd, Dd = torch.from_numpy(C).cuda(), torch.from_numpy(D).cuda()
+    out = {}
+    g1_flops, sy_flops = k_flops(cfg.naux, cfg.nao, cfg.nocc)
+    bufs = {}
+    for name, code, tdt in [("bf16", pkg.DFJK_BF16, torch.bfloat16), ("f16", pkg.DFJK_F16, torch.float16)]:
+        bufs[name] = (code, torch.empty((cfg.naux, cfg.npair), dtype=tdt, device="cuda"))
+    t0 = time.time()
+    rows = 512
+    for P0 in range(0, cfg.naux, rows):
+        blk = torch.from_numpy(synth.B_rows(cfg.seed, R, P0, rows)).cuda()
+        for name, (code, buf) in bufs.items():
+            pkg.dfjk_quantize(blk, buf[P0:P0 + rows], code, blk.numel())
+        torch.cuda.synchronize()
+        log(f"  rows {P0 + rows}/{cfg.naux} after {time.time() - t0:.0f} s")
+    del blk
+    for name, (code, buf) in bufs.items():
+        h = pkg.Handle(buf, cfg.nao, dtype=code)
+        r = time_steps(pkg, h, Dd, Cd, cfg, args.steps, args.warmup)
+        ph = r["phase_ms"]
+        jb = 2.0 * cfg.naux * cfg.npair * 2
+        out[name] = {"k_tflops": (g1_flops + sy_flops) / ph["K"] / 1e9, "j_hbm_gbs": jb / ph["J"] / 1e6,
+                     "ms_per_step": r["ms_per_step"], "phase_ms": ph,
+                     "k_gemm1_frac_of_f32_peak": g1_flops / ph["K_gemm1"] / 1e9 / PEAK["f32"],
+                     "j_frac_of_hbm": jb / ph["J"] / 1e6 / PEAK["hbm_gbs"]}
+        h.close()
+        log(name, out[name])
+    res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
+           "value": out["bf16"]["k_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": out["bf16"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 (B stored bf16/f16)", "data": "synthetic",
+           "config": {"workload": f"DF J/K build: nao={cfg.nao}, naux={cfg.naux}, nocc={cfg.nocc}, packed B "
+                                  f"stored BF16 and FP16 (34 GB each), J FP64 accumulation, K on FP32 "
+                                  f"matrix cores", "nao": cfg.nao, "naux": cfg.naux, "nocc": cfg.nocc},
+           "bf16": out["bf16"], "f16": out["f16"]}
+    print(json.dumps(res), flush=True)
+
+
+def bench_c4(args):
+    """256 molecules, nao ~ U{40..400}, naux = 4 nao, nocc = nao // 5, one
+    batched build per step (FP32 and BF16 storage); against a loop of
+    single-molecule builds and against the untuned tiles."""
+    import torch
+
+    import paper_2506_06661_amd as pkg
+    import synth
+
+    sizes = synth.batch_sizes()
+    res_d = {}
+    mols = {}
+    t0 = time.time()
+    for name, code, tdt in [("f32", pkg.DFJK_F32, torch.float32), ("bf16", pkg.DFJK_BF16, torch.bfloat16)]:
+        mols[name] = []
+    for i, nao in enumerate(sizes):
+        nao = int(nao)
+        seed = 4000 + i
+        R = synth.cluster_positions(seed, nao)
+        B = torch.from_numpy(synth.B_full(seed, R, 4 * nao)).cuda()
+        C = synth.C_occ(seed, nao, max(nao // 5, 1))
+        Cd = torch.from_numpy(C).cuda()
+        Dd = 2.0 * Cd @ Cd.T
+        for name, code, tdt in [("f32", pkg.DFJK_F32, torch.float32), ("bf16", pkg.DFJK_BF16, torch.bfloat16)]:
+            Bq = torch.empty(B.shape, dtype=tdt, device="cuda")
+            pkg.dfjk_quantize(B, Bq, code, B.numel())
+            mols[name].append({"B": Bq, "nao": nao, "D": Dd, "C": Cd,
+                               "J": torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                               "K": torch.empty((nao, nao), dtype=torch.float64, device="cuda")})
+        del B
+    torch.cuda.synchronize()
+    log(f"generated {len(sizes)} molecules in {time.time() - t0:.0f} s")
+    jbytes = {n: 0.0 for n in mols}
+    kfl = 0.0
+    for i, nao in enumerate(sizes):
+        nao = int(nao)
+        npair = nao * (nao + 1) // 2
+        g1, sy = k_flops(4 * nao, nao, max(nao // 5, 1))
+        kfl += g1 + sy
+        jbytes["f32"] += 2 * 4 * nao * npair * 4
+        jbytes["bf16"] += 2 * 4 * nao * npair * 2
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for name, code, _ in [("f32", pkg.DFJK_F32, None), ("bf16", pkg.DFJK_BF16, None)]:
+        bt = pkg.Batch(mols[name], code)
+        untuned = timed(bt.build, args.steps)
+        cache = os.path.join(ROOT, "gpurun_out", f"tiles_{name}.txt") if os.path.isdir(
+            os.path.join(ROOT, "gpurun_out")) else None
+        bt.autotune(reps=3, cache_path=None)
+        tiles = [bt.tile(b) for b in range(8)]
+        eager = timed(bt.build, args.steps)
+        bt.capture()
+        graph = timed(bt.launch, args.steps)
+        singles = [pkg.Handle(m["B"], m["nao"], dtype=code) for m in mols[name]]
+
+        def loop():
+            for hs, m in zip(singles, mols[name]):
+                pkg.dfjk_build_J(hs.h, m["D"], m["J"])
+                pkg.dfjk_build_K(hs.h, m["C"], m["C"].shape[1], None, m["K"])
+
+        single = timed(loop, max(1, args.steps // 2))
+        for hs in singles:
+            hs.close()
+        bt.close()
+        res_d[name] = {"graph_ms": graph, "eager_ms": eager, "untuned_eager_ms": untuned,
+                       "loop_of_single_builds_ms": single, "molecules_per_s": len(sizes) / graph * 1e3,
+                       "k_tflops_aggregate": kfl / graph / 1e9, "j_bytes_gb": jbytes[name] / 1e9,
+                       "tiles_by_bucket": tiles, "speedup_vs_loop": single / graph,
+                       "speedup_vs_untuned": untuned / graph}
+        log(name, res_d[name])
+        _ = cache
+    res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
+           "value": res_d["f32"]["molecules_per_s"], "unit": "molecules/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1, "ms_per_step": res_d["f32"]["graph_ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"batched DF J/K: {len(sizes)} molecules, nao ~ U{{40..400}} "
+                                  f"(sum {int(sizes.sum())}), naux = 4 nao, nocc = nao//5, one graph-captured "
+                                  f"batched J+K per step", "nmol": int(len(sizes))},
+           "f32": res_d["f32"], "bf16": res_d["bf16"]}
+    print(json.dumps(res), flush=True)
+
+
+def bench_c5(args):
+    """Learned guess: train on the plain SCF's converged densities of
+    n_train systems (nao=128, naux=512, nocc=24), then count J/K builds to
+    1e-6 Eh on n_test held-out systems, learned guess against core guess."""
+    import torch
+
+    import paper_2506_06661_amd as pkg
+    import synth
+    from paper_2506_06661_amd import guess
+
+    cfg = synth.C5
+
+    def system(seed):
+        R, B, H = synth.scf_system(seed, cfg)
+        return pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao), torch.from_numpy(H).cuda(), \
+            torch.from_numpy(R).cuda()
+
+    t0 = time.time()
+    Xs, ts, nconv, scf_ms = [], [], 0, []
+    for seed in range(args.n_train):
+        h, H, R = system(seed)
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        recs, D, C = guess.run_scf(h, H, cfg.nocc)
+        scf_ms.append((time.perf_counter() - ts0) * 1e3)
+        if recs[-1][2]:
+            nconv += 1
+            _, Dc = guess.core_guess(h, H, cfg.nocc)
+            Xs.append(guess.features(H, Dc, R))
+            ts.append(guess.packed(D - Dc).float())
+        h.close()
+        if seed % 200 == 0:
+            log(f"  training data {seed}/{args.n_train}, {time.time() - t0:.0f} s")
+    X = torch.cat(Xs).contiguous()
+    t = torch.cat(ts).contiguous()
+    mlp = pkg.MLP(8, 256, 65536)
+    tr = guess.Trainer(mlp, synth.uniform(1, synth.STREAM_MLP, mlp.nparam))
+    torch.cuda.synchronize()
+    tt = time.perf_counter()
+    tr.fit(X, t, epochs=args.epochs, batch=65536, lr=1e-3,
+           order_uniform=synth.uniform(2, synth.STREAM_MLP, X.shape[0] * args.epochs), log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - tt
+    core, learned, fb, fails = [], [], 0, 0
+    for seed in range(2000, 2000 + args.n_test):
+        h, H, R = system(seed)
+        ref, _, _ = guess.run_scf(h, H, cfg.nocc)
+        if not ref[-1][2]:
+            fails += 1
+            h.close()
+            continue
+        e_ref = ref[-1][0]
+        core.append(guess.builds_to(ref, e_ref))
+        out = guess.solve(h, tr, H, R, cfg.nocc, e_ref=e_ref)
+        learned.append(out["builds"])
+        fb += out["fallback"]
+        h.close()
+    core, learned = np.array(core, float), np.array(learned, float)
+    res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
+           "value": float(learned.mean()), "unit": "J/K builds to 1e-6 Eh (mean)", "n_gpus": 1,
+           "steps": int(len(learned)), "warmup": 0, "ms_per_step": float(np.mean(scf_ms)),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64 SCF, f32 MLP",
+           "data": "synthetic",
+           "config": {"workload": f"learned guess: nao={cfg.nao}, naux={cfg.naux}, nocc={cfg.nocc}, "
+                                  f"{args.n_train} training systems, {args.n_test} held out, "
+                                  f"B scaled by {synth.C5_B_SCALE}", "epochs": args.epochs},
+           "core_guess_builds_mean": float(core.mean()), "core_guess_builds_median": float(np.median(core)),
+           "learned_builds_mean": float(learned.mean()), "learned_builds_median": float(np.median(learned)),
+           "paired_mean_difference": float((learned - core).mean()),
+           "fallbacks": int(fb), "test_systems_not_converged_plain": int(fails),
+           "train_systems_converged": int(nconv), "train_pairs": int(X.shape[0]),
+           "train_seconds": train_s, "plain_scf_ms_mean": float(np.mean(scf_ms))}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: nao=1024 FP64 (+FP32) single builds (default); c3: nao=2048 BF16/FP16; "
+                         "c4: 256-molecule batch; c5: learned-guess SCF experiment")
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--n-test", type=int, default=200)
+    ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--cpu-rows", type=int, default=1024,
@@ -116,6 +363,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
+    if args.workload == "c3":
+        return bench_c3(args)
+    if args.workload == "c4":
+        return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
     cfg = synth.C2
     t0 = time.time()
     R = synth.positions(cfg)
@@ -215,6 +468,22 @@ def main():
         },
     }
     h.close()
+    if args.dtype == "f64":
+        # the same workload with B stored in FP32 (one RNE step from FP64)
+        Bf = torch.empty(Bd.shape, dtype=torch.float32, device="cuda")
+        pkg.dfjk_quantize(Bd, Bf, pkg.DFJK_F32, Bd.numel())
+        h32 = pkg.Handle(Bf, cfg.nao, dtype=pkg.DFJK_F32)
+        f32 = time_steps(pkg, h32, Dd, Cd, cfg, args.steps, args.warmup)
+        g1_32 = f32["phase_ms"]["K_gemm1"]
+        res["f32"] = {
+            "k_tflops": (g1_flops + sy_flops) / f32["phase_ms"]["K"] / 1e9,
+            "j_hbm_gbs": jbytes / 2 / f32["phase_ms"]["J"] / 1e6,
+            "ms_per_step": f32["ms_per_step"], "phase_ms": f32["phase_ms"],
+            "k_gemm1_frac_of_f32_peak": g1_flops / g1_32 / 1e9 / PEAK["f32"],
+            "speedup_vs_f64_step": res["ms_per_step"] / f32["ms_per_step"],
+        }
+        h32.close()
+        del Bf
     del Bd, Cd, Dd
     if args.cpu_rows > 0:
         log(f"timing the CPU oracle on {args.cpu_rows} aux rows ...")

@@ -22,7 +22,8 @@
  *   C   nao x nocc FP64 (row mu, column i).
  *
  * Ownership: the caller owns every array.  dfjk_init borrows B for the life
- * of the handle and never writes it.  The handle owns its workspace, which
+ * of the handle and never writes it (with the k16 option the handle also keeps
+ * a dense 16-bit copy of it).  The handle owns its workspace, which
  * it allocates in dfjk_init and, when a call needs more (a larger nocc),
  * in that call.
  *
@@ -73,6 +74,11 @@ typedef struct {
     int max_cycle;        /* SCF iteration cap (100) */
     int compensated_j;    /* reduced-precision B, J accumulation: 2 = FP64 (default),
                              1 = compensated FP32 (Dot2), 0 = plain FP32 */
+    int k16;              /* BF16/FP16 B, exchange from C: 1 = 16-bit matrix cores
+                             (the handle keeps a dense 16-bit copy of B, naux *
+                             ceil32(nao)^2 elements, made on the first K call; C
+                             and X rounded to the 16-bit format); 0 = B
+                             dequantised on load, FP32 matrix cores (default) */
 } dfjk_options;
 
 /* Fills *o with the defaults. */
@@ -147,6 +153,14 @@ enum { DFJK_SCF_C_VALID = 1 };
 int dfjk_scf_step(dfjk_handle h, const double* H_dev, double* D_dev, double* Cocc_dev, int64_t nocc,
                   int flags, dfjk_scf_info* info);
 
+/*
+ * Aufbau occupation of a symmetric nao x nao matrix F (e.g. the core
+ * Hamiltonian for the core guess): Cocc <- eigenvectors of the nocc lowest
+ * eigenvalues (nao x nocc), and, if D_dev is not NULL, D <- 2 C C^T.  Uses
+ * the handle's eigensolver workspace and stream (nao <= 4096).
+ */
+int dfjk_aufbau(dfjk_handle h, const double* F_dev, int64_t nocc, double* Cocc_dev, double* D_dev);
+
 /* Forget the SCF iteration count and the DIIS history. */
 int dfjk_scf_reset(dfjk_handle h);
 
@@ -173,13 +187,14 @@ int dfjk_profile_read(dfjk_handle h, double* total_ms, int* counts, int nphase);
 
 /*
  * Tile shapes (for autotuning).  DFJK_TILE_GEMM1 selects the X = B_P C
- * kernel's workgroup tile.  dfjk_tile_count returns the number of compiled
- * tiles; dfjk_tile_info gives tile `index` as (p0, p1) = (row tiles of 16
- * occupied orbitals, column tiles of 16 basis functions per wavefront);
- * dfjk_set_tile makes the handle use tile `index` (-1 = built-in heuristic).
- * Every tile computes the same X up to summation order.
+ * kernel's workgroup tile: dfjk_tile_info gives (p0, p1) = (row tiles of 16
+ * occupied orbitals, column tiles of 16 basis functions per wavefront).
+ * DFJK_TILE_J_OUT selects the FP64 J pass-2 column width: (p0, p1) =
+ * (packed columns per workgroup, 0).  dfjk_tile_count returns the number of
+ * compiled tiles; dfjk_set_tile makes the handle use tile `index` (-1 =
+ * default).  Every tile computes the same result up to summation order.
  */
-enum { DFJK_TILE_GEMM1 = 0 };
+enum { DFJK_TILE_GEMM1 = 0, DFJK_TILE_J_OUT = 1 };
 int dfjk_tile_count(int kernel);
 int dfjk_tile_info(int kernel, int index, int* p0, int* p1);
 int dfjk_set_tile(dfjk_handle h, int kernel, int index);

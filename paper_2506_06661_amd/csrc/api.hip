@@ -60,6 +60,7 @@ void dfjk_default_options(dfjk_options* o) {
     o->conv_tol_grad = 3e-5;
     o->max_cycle = 100;
     o->compensated_j = 2;
+    o->k16 = 0;
 }
 
 const char* dfjk_last_error(void) { return g_err; }
@@ -117,7 +118,7 @@ int dfjk_init(dfjk_handle* out, const void* B_dev, int dtype, int64_t nao, int64
     else
         dfjk_default_options(&h->opts);
     if (h->opts.diis_space < 1 || h->opts.diis_space > 15 || h->opts.max_cycle < 1 ||
-        h->opts.compensated_j < 0 || h->opts.compensated_j > 2) {
+        h->opts.compensated_j < 0 || h->opts.compensated_j > 2 || h->opts.k16 < 0 || h->opts.k16 > 1) {
         delete h;
         set_error("dfjk_init: options out of range (diis_space 1..15, compensated_j 0..2)");
         return DFJK_E_INVALID;
@@ -200,6 +201,16 @@ int dfjk_scf_step(dfjk_handle h, const double* H_dev, double* D_dev, double* Coc
     return scf_step(h, H_dev, D_dev, Cocc_dev, nocc, flags, info);
 }
 
+int dfjk_aufbau(dfjk_handle h, const double* F_dev, int64_t nocc, double* Cocc_dev, double* D_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!F_dev || !Cocc_dev || nocc < 1 || nocc > h->nao) {
+        set_error("dfjk_aufbau: null F or Cocc, or nocc outside [1, nao]");
+        return DFJK_E_INVALID;
+    }
+    return aufbau(h, F_dev, nocc, Cocc_dev, D_dev);
+}
+
 int dfjk_scf_reset(dfjk_handle h) {
     clear_error();
     if (int rc = check_handle(h)) return rc;
@@ -208,18 +219,27 @@ int dfjk_scf_reset(dfjk_handle h) {
 
 int dfjk_tile_count(int kernel) {
     clear_error();
-    if (kernel != DFJK_TILE_GEMM1) {
-        set_error("dfjk_tile_count: unknown kernel %d", kernel);
-        return DFJK_E_INVALID;
-    }
-    return k_tile_count();
+    if (kernel == DFJK_TILE_GEMM1) return k_tile_count();
+    if (kernel == DFJK_TILE_J_OUT) return j_out_count();
+    set_error("dfjk_tile_count: unknown kernel %d", kernel);
+    return DFJK_E_INVALID;
 }
 
 int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
     clear_error();
-    if (kernel != DFJK_TILE_GEMM1 || !p0 || !p1) {
+    if ((kernel != DFJK_TILE_GEMM1 && kernel != DFJK_TILE_J_OUT) || !p0 || !p1) {
         set_error("dfjk_tile_info: unknown kernel or null output");
         return DFJK_E_INVALID;
+    }
+    if (kernel == DFJK_TILE_J_OUT) {
+        static const int widths[] = {2, 4, 8, 16};
+        if (index < 0 || index >= j_out_count()) {
+            set_error("dfjk_tile_info: index %d out of range", index);
+            return DFJK_E_INVALID;
+        }
+        *p0 = 512 * widths[index];
+        *p1 = 0;
+        return DFJK_OK;
     }
     if (k_tile_info(index, p0, p1) != DFJK_OK) {
         set_error("dfjk_tile_info: index %d out of range", index);
@@ -231,11 +251,16 @@ int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
 int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
     clear_error();
     if (int rc = check_handle(h)) return rc;
-    if (kernel != DFJK_TILE_GEMM1 || index < -1 || index >= k_tile_count()) {
+    const int count = kernel == DFJK_TILE_GEMM1 ? k_tile_count()
+                      : kernel == DFJK_TILE_J_OUT ? j_out_count() : 0;
+    if (count == 0 || index < -1 || index >= count) {
         set_error("dfjk_set_tile: kernel %d / index %d invalid", kernel, index);
         return DFJK_E_INVALID;
     }
-    h->g1_tile = index;
+    if (kernel == DFJK_TILE_GEMM1)
+        h->g1_tile = index;
+    else
+        h->jout_tile = index;
     return DFJK_OK;
 }
 
@@ -247,7 +272,7 @@ int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes) {
         return DFJK_E_INVALID;
     }
     *bytes = h->dt.bytes + h->rho_part.bytes + h->rho.bytes + h->jpart.bytes + h->X.bytes +
-             h->kpart.bytes + h->ones.bytes + h->Cw.bytes + h->eig.bytes;
+             h->kpart.bytes + h->ones.bytes + h->Cw.bytes + h->eig.bytes + h->Bdense.bytes;
     return DFJK_OK;
 }
 
@@ -333,6 +358,7 @@ void dfjk_destroy(dfjk_handle h) {
     h->ones.release();
     h->Cw.release();
     h->eig.release();
+    h->Bdense.release();
     delete h;
 }
 

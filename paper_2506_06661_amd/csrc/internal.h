@@ -82,8 +82,11 @@ struct dfjk_ctx {
     dfjk::DevBuf ones;      // default +1 signs
     dfjk::DevBuf Cw;        // staged (converted) C
     dfjk::DevBuf eig;       // eigen-work for the D path
+    dfjk::DevBuf Bdense;    // dense 16-bit copy of B for the 16-bit exchange (opts.k16)
+    bool dense_ready = false;
 
     int g1_tile = -1;       // GEMM1 tile index (-1: heuristic)
+    int jout_tile = -1;     // J pass-2 column width index (-1: default)
 
     // SCF state (scf.hip): iterations done, DIIS vectors stored
     int scf_iter = 0, scf_count = 0;
@@ -97,14 +100,17 @@ namespace dfjk {
 // J launchers (j_kernels.hip)
 int j_setup(dfjk_ctx* h);
 int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out);
+int j_out_count();
 
 // K launchers (k_kernels.hip)
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
                      double* K);
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K);
+int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K);
 int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, int flags,
              dfjk_scf_info* info);
 int scf_reset(dfjk_ctx* h);
+int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D);
 int k_tile_count();
 int k_tile_info(int t, int* ni, int* wm);
 

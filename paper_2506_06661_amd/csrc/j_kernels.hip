@@ -24,8 +24,6 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
 constexpr int kRhoRows = 4;     // rows of B per workgroup in pass 1
-constexpr int kOutVec = 2;      // double2 loads per row per thread in pass 2
-constexpr int kOutCols = kThreads * 2 * kOutVec;  // columns per workgroup in pass 2
 
 // dt[p(mu,nu)] for all mu <= nu; one block per row nu of the packed triangle.
 __device__ inline void pack_density_body(int64_t nu, const double* __restrict__ D, int64_t nao,
@@ -121,28 +119,31 @@ __global__ void j_rho_finish(const double* __restrict__ part, int64_t naux, int 
     rho_finish_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, part, naux, nchunk, rho, rho_out);
 }
 
-template <bool VEC>
+// U = double2 loads per row per thread: a workgroup owns 512*U packed columns
+// (a 4U-KB run of each row it visits).
+template <bool VEC, int U>
 __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__ B, int64_t ldB,
                                                        int64_t naux, int64_t npair,
                                                        const double* __restrict__ rho, int64_t prows,
                                                        double* __restrict__ jpart) {
+    constexpr int64_t COLS = (int64_t)kThreads * 2 * U;
     const int s = blockIdx.y;
     const int64_t P0 = (int64_t)s * prows;
     const int64_t P1 = P0 + prows < naux ? P0 + prows : naux;
-    const int64_t base = (int64_t)blockIdx.x * kOutCols;
-    double acc[2 * kOutVec];
+    const int64_t base = (int64_t)blockIdx.x * COLS;
+    double acc[2 * U];
 #pragma unroll
-    for (int u = 0; u < 2 * kOutVec; ++u) acc[u] = 0.0;
+    for (int u = 0; u < 2 * U; ++u) acc[u] = 0.0;
     // columns of this thread: base + u*2*kThreads + 2*tid + {0,1}
     const int64_t col0 = base + 2 * (int64_t)threadIdx.x;
-    const bool full = base + kOutCols <= npair;
+    const bool full = base + COLS <= npair;
     if (VEC && full) {
-#pragma unroll 4
+#pragma unroll 2
         for (int64_t P = P0; P < P1; ++P) {
             const double r = rho[P];
             const double* row = B + P * ldB + col0;
 #pragma unroll
-            for (int u = 0; u < kOutVec; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2*>(row + u * 2 * kThreads));
                 acc[2 * u] = fma(b.x, r, acc[2 * u]);
                 acc[2 * u + 1] = fma(b.y, r, acc[2 * u + 1]);
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
             const double r = rho[P];
             const double* row = B + P * ldB;
 #pragma unroll
-            for (int u = 0; u < kOutVec; ++u) {
+            for (int u = 0; u < U; ++u) {
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int64_t col = col0 + u * 2 * kThreads + e;
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
     }
     double* out = jpart + (int64_t)s * npair;
 #pragma unroll
-    for (int u = 0; u < kOutVec; ++u) {
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int64_t col = col0 + u * 2 * kThreads + e;
@@ -172,6 +173,18 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
         }
     }
 }
+
+template <int U>
+void launch_j_out(bool vec, dim3 g, hipStream_t st, const double* B, int64_t ldB, int64_t naux,
+                  int64_t npair, const double* rho, int64_t prows, double* jpart) {
+    if (vec)
+        j_out_f64<true, U><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart);
+    else
+        j_out_f64<false, U><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart);
+}
+
+constexpr int kJOutU[] = {2, 4, 8, 16};
+constexpr int kNumJOut = 4;
 
 // J[nu,mu] = J[mu,nu] = sum_s jpart[s][p(mu,nu)]; one block per packed row nu.
 __device__ inline void j_finish_body(int64_t nu, const double* __restrict__ jpart, int64_t npair,
@@ -493,6 +506,18 @@ int j_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, cons
     return DFJK_OK;
 }
 
+// Pass-2 geometry for column width U: (column blocks) x (row slices) ~ 4096.
+static void j_out_geometry(const dfjk_ctx* h, int U, int64_t* splits_out) {
+    const int64_t colblocks = cdiv(h->npair, (int64_t)kThreads * 2 * U);
+    int64_t splits = cdiv(4096, colblocks);
+    if (splits > h->naux) splits = h->naux;
+    if (splits < 1) splits = 1;
+    if (splits > 128) splits = 128;
+    *splits_out = splits;
+}
+
+int j_out_count() { return kNumJOut; }
+
 int j_setup(dfjk_ctx* h) {
     const int64_t rowblocks = cdiv(h->naux, kRhoRows);
     // pass 1: enough (row block, chunk) workgroups to cover the chip several times
@@ -502,12 +527,13 @@ int j_setup(dfjk_ctx* h) {
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
     h->j_chunks = (int)chunks;
-    // pass 2: row slices so that (column blocks x slices) covers the chip
-    const int64_t colblocks = cdiv(h->npair, kOutCols);
-    int64_t splits = cdiv(4096, colblocks);
-    if (splits > h->naux) splits = h->naux;
-    if (splits < 1) splits = 1;
-    if (splits > 64) splits = 64;
+    // pass 2: the largest row slice count any column width needs
+    int64_t splits = 1;
+    for (int t = 0; t < kNumJOut; ++t) {
+        int64_t sp;
+        j_out_geometry(h, kJOutU[t], &sp);
+        if (sp > splits) splits = sp;
+    }
     h->j_splits = (int)splits;
     int rc;
     if ((rc = h->dt.ensure(sizeof(double) * (size_t)h->npair * 3))) return rc;
@@ -551,16 +577,22 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out) {
                                                                        rho_out);
     DFJK_LAUNCH_CHECK("j_rho_finish");
 
-    const int64_t prows = cdiv(h->naux, h->j_splits);
-    const dim3 g2((unsigned)cdiv(h->npair, kOutCols), (unsigned)h->j_splits);
+    const int t = h->jout_tile >= 0 && h->jout_tile < kNumJOut ? h->jout_tile : 0;
+    const int U = kJOutU[t];
+    int64_t splits;
+    j_out_geometry(h, U, &splits);
+    const int64_t prows = cdiv(h->naux, splits);
+    const dim3 g2((unsigned)cdiv(h->npair, (int64_t)kThreads * 2 * U), (unsigned)splits);
     h->prof.begin(PH_J_OUT, st);
-    if (vec)
-        j_out_f64<true><<<g2, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, rho, prows, jpart);
-    else
-        j_out_f64<false><<<g2, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, rho, prows, jpart);
+    switch (U) {
+        case 2: launch_j_out<2>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
+        case 4: launch_j_out<4>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
+        case 8: launch_j_out<8>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
+        default: launch_j_out<16>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
+    }
     h->prof.end(PH_J_OUT, st);
     DFJK_LAUNCH_CHECK("j_out_f64");
-    j_finish<<<dim3((unsigned)h->nao), kThreads, 0, st>>>(jpart, h->npair, h->j_splits, h->nao, J);
+    j_finish<<<dim3((unsigned)h->nao), kThreads, 0, st>>>(jpart, h->npair, (int)splits, h->nao, J);
     h->prof.end(PH_J, st);
     DFJK_LAUNCH_CHECK("j_finish");
     return DFJK_OK;

@@ -1,0 +1,329 @@
+// Exchange on the 16-bit matrix cores (v_mfma_f32_16x16x32_bf16 / _f16) for B
+// stored in BF16 or FP16.
+//
+// Both operands of a 16-bit matrix-core step carry 8 consecutive contraction
+// indices per lane (lane l: A[l%16][8(l/16)+j], B[8(l/16)+j][l%16], j < 8;
+// result row 4(l/16)+r, column l%16 in FP32).  The packed triangle is
+// contiguous along the contraction index only below the diagonal, so the
+// handle keeps a dense 16-bit copy of every B_P (both triangles, row length
+// padded to a multiple of 32 with zeros), made once with an LDS-tiled
+// transpose.  Then
+//   GEMM1: X[P][mu][i] = sum_nu Bd_P[mu][nu] Ct[i][nu]   (Ct = C^T in 16 bits)
+//   GEMM2: K[mu][nu]   = 2 sum_{P,i} X[P][mu][i] X[P][nu][i]
+// with X stored in 16 bits, rows (P, mu) of ncp (nocc padded to 32) entries,
+// so both products read 16-byte runs along the contraction index.  Products
+// accumulate in FP32; split partials are added in FP64.
+#include "internal.h"
+#include "mma.h"
+#include "numerics.h"
+
+namespace dfjk {
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;
+constexpr int KS = 32;         // contraction chunk (one matrix-core step)
+constexpr int LROW = KS + 8;   // LDS row: 32 halves + 8 of padding (80 bytes)
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename H>
+struct Mma16;
+template <>
+struct Mma16<uint16_t> {  // bfloat16 bits
+    __device__ static v4f step(u4 a, u4 b, v4f c) {
+        v8bf av, bv;
+        __builtin_memcpy(&av, &a, 16);
+        __builtin_memcpy(&bv, &b, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    }
+    __device__ static uint16_t from_float(float f) { return float_to_bf16_rne(f); }
+    __device__ static uint16_t from_double(double x) { return float_to_bf16_rne(to_float_round_odd(x)); }
+};
+template <>
+struct Mma16<_Float16> {
+    __device__ static v4f step(u4 a, u4 b, v4f c) {
+        v8h av, bv;
+        __builtin_memcpy(&av, &a, 16);
+        __builtin_memcpy(&bv, &b, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
+    }
+    __device__ static _Float16 from_float(float f) { return (_Float16)f; }
+    __device__ static _Float16 from_double(double x) { return (_Float16)to_float_round_odd(x); }
+};
+
+// ---------------------------------------------------------------- dense copy
+// Tile (I >= J) of 64 x 64 of the lower block triangle of B_P: packed rows
+// nu in I, columns mu in J (mu <= nu) -> Bd[nu][mu] and Bd[mu][nu].  Elements
+// outside the triangle or the matrix become zero, so the pad is zero too.
+template <typename H>
+__global__ __launch_bounds__(kT) void dense_copy(const H* __restrict__ B, int64_t ldB, int64_t nao,
+                                                  int64_t ldd, int64_t ntile, H* __restrict__ Bd) {
+    __shared__ H tile[64][65];
+    const int64_t P = blockIdx.y;
+    const int64_t t = blockIdx.x;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int64_t J = t - I * (I + 1) / 2;
+    const int64_t nu0 = I * 64, mu0 = J * 64;
+    const H* Bp = B + P * ldB;
+    H* D = Bd + P * ldd * ldd;
+    for (int e = threadIdx.x; e < 64 * 64; e += kT) {
+        const int a = e / 64, b = e % 64;  // row nu0+a, column mu0+b
+        const int64_t nu = nu0 + a, mu = mu0 + b;
+        H v = H(0);
+        if (nu < nao && mu <= nu) v = Bp[nu * (nu + 1) / 2 + mu];
+        tile[a][b] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += kT) {
+        const int a = e / 64, b = e % 64;
+        const int64_t nu = nu0 + a, mu = mu0 + b;
+        if (nu < ldd && mu < ldd && mu <= nu) D[nu * ldd + mu] = tile[a][b];  // lower half
+        // transposed: row mu0+a, column nu0+b holds B[nu0+b][mu0+a]
+        const int64_t r = mu0 + a, c = nu0 + b;
+        if (r < ldd && c < ldd && r < c) D[r * ldd + c] = tile[b][a];
+    }
+    (void)ntile;
+}
+
+// Ct[i][nu] = C[nu][i] rounded once to the 16-bit format, for i < ncp,
+// nu < ldd (zero outside C)
+template <typename H>
+__global__ void c_transpose(const double* __restrict__ C, int64_t nao, int64_t ncol, int64_t ncp,
+                            int64_t ldd, H* __restrict__ Ct) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ncp * ldd) return;
+    const int64_t i = e / ldd, nu = e % ldd;
+    const double v = (i < ncol && nu < nao) ? C[nu * ncol + i] : 0.0;
+    Ct[e] = Mma16<H>::from_double(v);
+}
+
+// ---------------------------------------------------------------- GEMM1
+// Workgroup: 128 rows mu (4 waves x 32) x 16*NI columns i, one P.
+template <typename H, int NI>
+__global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ldd, int64_t nao,
+                                             const H* __restrict__ Ct, int64_t ncol, int64_t ncp,
+                                             H* __restrict__ X, int64_t nib, int64_t nmb, int64_t nblk) {
+    constexpr int BI = 16 * NI, BM = 128;
+    __shared__ H sA[BM][LROW];
+    __shared__ H sB[BI][LROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t lid = [&] {
+        constexpr int64_t NX = 8;
+        const int64_t per = nblk / NX, rem = nblk % NX, x = blockIdx.x % NX, q = blockIdx.x / NX;
+        const int64_t start = x * per + (x < rem ? x : rem);
+        return start + q;
+    }();
+    const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
+    const int64_t i0 = ib * BI, mu0 = mb * BM;
+    const H* A = Bd + P * ldd * ldd;
+    v4f acc[2][NI];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t nk = ldd / KS;
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const int64_t k0 = kc * KS;
+        // A: 128 rows x 32 halves = 512 16-byte pieces; B: BI rows x 32 = 4*BI pieces
+        for (int e = tid; e < BM * 4; e += kT) {
+            const int r = e >> 2, q = e & 3;
+            const int64_t mu = mu0 + r;
+            u4 v = u4{0u, 0u, 0u, 0u};
+            if (mu < ldd) v = *reinterpret_cast<const u4*>(A + mu * ldd + k0 + 8 * q);
+            *reinterpret_cast<u4*>(&sA[r][8 * q]) = v;
+        }
+        for (int e = tid; e < BI * 4; e += kT) {
+            const int r = e >> 2, q = e & 3;
+            const int64_t i = i0 + r;
+            u4 v = u4{0u, 0u, 0u, 0u};
+            if (i < ncp) v = *reinterpret_cast<const u4*>(Ct + i * ldd + k0 + 8 * q);
+            *reinterpret_cast<u4*>(&sB[r][8 * q]) = v;
+        }
+        __syncthreads();
+        u4 a[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            a[t] = *reinterpret_cast<const u4*>(&sA[wave * 32 + t * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int n = 0; n < NI; ++n) {
+            const u4 b = *reinterpret_cast<const u4*>(&sB[n * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) acc[t][n] = Mma16<H>::step(a[t], b, acc[t][n]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int n = 0; n < NI; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t mu = mu0 + wave * 32 + t * 16 + 4 * (lane >> 4) + r;
+                const int64_t i = i0 + n * 16 + (lane & 15);
+                if (mu < nao && i < ncp)
+                    X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[t][n][r] : 0.f);
+            }
+}
+
+// ---------------------------------------------------------------- GEMM2
+// Lower tile (I >= J) of 128 x 128 of K; 2 x 2 waves of 64 x 64; the
+// contraction over (P, i) runs in 32-wide steps inside each P.
+template <typename H>
+__global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t nao, int64_t ncp,
+                                               int64_t naux, int64_t pchunk, int64_t ntl, int64_t nblk,
+                                               float* __restrict__ part) {
+    __shared__ H sA[128][LROW];
+    __shared__ H sB[128][LROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t lid = [&] {
+        constexpr int64_t NX = 8;
+        const int64_t per = nblk / NX, rem = nblk % NX, x = blockIdx.x % NX, q = blockIdx.x / NX;
+        return x * per + (x < rem ? x : rem) + q;
+    }();
+    const int64_t t = lid % ntl, s = lid / ntl;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int64_t J = t - I * (I + 1) / 2;
+    const int64_t mu0 = I * 128, nu0 = J * 128;
+    const int64_t P0 = s * pchunk, P1 = P0 + pchunk < naux ? P0 + pchunk : naux;
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t nks = ncp / KS;
+    for (int64_t P = P0; P < P1; ++P) {
+        const H* XP = X + P * nao * ncp;
+        for (int64_t kc = 0; kc < nks; ++kc) {
+            const int64_t k0 = kc * KS;
+            for (int e = tid; e < 128 * 4; e += kT) {
+                const int r = e >> 2, q = e & 3;
+                u4 va = u4{0u, 0u, 0u, 0u}, vb = u4{0u, 0u, 0u, 0u};
+                if (mu0 + r < nao) va = *reinterpret_cast<const u4*>(XP + (mu0 + r) * ncp + k0 + 8 * q);
+                if (nu0 + r < nao) vb = *reinterpret_cast<const u4*>(XP + (nu0 + r) * ncp + k0 + 8 * q);
+                *reinterpret_cast<u4*>(&sA[r][8 * q]) = va;
+                *reinterpret_cast<u4*>(&sB[r][8 * q]) = vb;
+            }
+            __syncthreads();
+            u4 a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = *reinterpret_cast<const u4*>(&sA[wm * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+                b[q] = *reinterpret_cast<const u4*>(&sB[wn * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = Mma16<H>::step(a[ti], b[tj], acc[ti][tj]);
+            __syncthreads();
+        }
+    }
+    float* out = part + (s * ntl + t) * (int64_t)(128 * 128);
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = wm * 64 + ti * 16 + 4 * (lane >> 4) + r;
+                const int n = wn * 64 + tj * 16 + (lane & 15);
+                out[m * 128 + n] = acc[ti][tj][r];
+            }
+}
+
+// K = scale * sum_s part[s][t] over the lower triangle, mirrored (diagonal
+// tiles use m >= n only, so K is exactly symmetric).
+__global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ part, int64_t nsplit,
+                                                     int64_t ntl, int64_t nao, double scale,
+                                                     double* __restrict__ K) {
+    const int64_t t = blockIdx.x;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int64_t J = t - I * (I + 1) / 2;
+    for (int e = threadIdx.x; e < 128 * 128; e += kT) {
+        const int m = e / 128, n = e % 128;
+        const int64_t mu = I * 128 + m, nu = J * 128 + n;
+        if (mu >= nao || nu >= nao || (I == J && m < n)) continue;
+        double v = 0.0;
+        for (int64_t s = 0; s < nsplit; ++s) v += (double)part[(s * ntl + t) * (int64_t)(128 * 128) + e];
+        v *= scale;
+        K[mu * nao + nu] = v;
+        K[nu * nao + mu] = v;
+    }
+}
+
+template <typename H, int NI>
+void launch_g1(hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
+               int64_t ncp, H* X, int64_t naux) {
+    const int64_t nib = cdiv(ncp, 16 * NI), nmb = cdiv(nao, 128);
+    const int64_t nblk = nib * nmb * naux;
+    g1_16<H, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
+}
+
+template <typename H>
+int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
+    const hipStream_t st = h->stream;
+    const int64_t nao = h->nao, naux = h->naux;
+    const int64_t ldd = cdiv(nao, KS) * KS;
+    const int64_t ncp = cdiv(ncol, KS) * KS;
+    int rc;
+    if (!h->dense_ready) {
+        if ((rc = h->Bdense.ensure(sizeof(H) * (size_t)naux * (size_t)(ldd * ldd)))) return rc;
+        const int64_t nt = cdiv(ldd, 64), ntile = nt * (nt + 1) / 2;
+        dense_copy<H><<<dim3((unsigned)ntile, (unsigned)naux), kT, 0, st>>>(
+            static_cast<const H*>(h->B), h->ldB, nao, ldd, ntile, static_cast<H*>(h->Bdense.ptr));
+        DFJK_LAUNCH_CHECK("dense_copy");
+        h->dense_ready = true;
+    }
+    if ((rc = h->Cw.ensure(sizeof(H) * (size_t)(ncp * ldd)))) return rc;
+    if ((rc = h->X.ensure(sizeof(H) * (size_t)(naux * nao * ncp)))) return rc;
+    H* Ct = static_cast<H*>(h->Cw.ptr);
+    H* X = static_cast<H*>(h->X.ptr);
+    const H* Bd = static_cast<const H*>(h->Bdense.ptr);
+    h->prof.begin(PH_K, st);
+    c_transpose<H><<<dim3((unsigned)cdiv(ncp * ldd, 256)), 256, 0, st>>>(C, nao, ncol, ncp, ldd, Ct);
+    DFJK_LAUNCH_CHECK("c_transpose");
+    h->prof.begin(PH_K_GEMM1, st);
+    if (ncp <= 64) launch_g1<H, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    else launch_g1<H, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    h->prof.end(PH_K_GEMM1, st);
+    DFJK_LAUNCH_CHECK("g1_16");
+    const int64_t nt = cdiv(nao, 128), ntl = nt * (nt + 1) / 2;
+    int64_t nsplit = cdiv(2048, ntl);
+    if (nsplit > naux) nsplit = naux;
+    const int64_t pchunk = cdiv(naux, nsplit);
+    nsplit = cdiv(naux, pchunk);
+    if ((rc = h->kpart.ensure(sizeof(float) * (size_t)(nsplit * ntl) * 128 * 128))) return rc;
+    float* part = static_cast<float*>(h->kpart.ptr);
+    h->prof.begin(PH_K_SYRK, st);
+    syrk_16<H><<<dim3((unsigned)(ntl * nsplit)), kT, 0, st>>>(X, nao, ncp, naux, pchunk, ntl,
+                                                                ntl * nsplit, part);
+    h->prof.end(PH_K_SYRK, st);
+    DFJK_LAUNCH_CHECK("syrk_16");
+    h->prof.begin(PH_K_FINISH, st);
+    syrk16_finish<<<dim3((unsigned)ntl), kT, 0, st>>>(part, nsplit, ntl, nao, scale, K);
+    h->prof.end(PH_K_FINISH, st);
+    h->prof.end(PH_K, st);
+    DFJK_LAUNCH_CHECK("syrk16_finish");
+    return DFJK_OK;
+}
+
+}  // namespace
+
+int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
+    if (h->dtype == DFJK_BF16) return k16_t<uint16_t>(h, C, ncol, scale, K);
+    if (h->dtype == DFJK_F16) return k16_t<_Float16>(h, C, ncol, scale, K);
+    set_error("16-bit exchange needs BF16 or FP16 B");
+    return DFJK_E_DTYPE;
+}
+
+}  // namespace dfjk

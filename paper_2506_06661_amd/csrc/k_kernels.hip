@@ -575,6 +575,8 @@ int tile_nb(int tile, int64_t nao, int64_t ncol, int64_t* nib, int64_t* nmb) {
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
                      double* K) {
     if (h->dtype == DFJK_F64) return k_build_t<double>(h, C, ncol, sign, scale, K);
+    if ((h->dtype == DFJK_BF16 || h->dtype == DFJK_F16) && h->opts.k16 && !sign)
+        return k_build_16(h, C, ncol, scale, K);
     {  // FP32 compute for FP32, BF16 and FP16 storage of B
         int rc;
         if ((rc = h->Cw.ensure(sizeof(float) * (size_t)(h->nao * ncol)))) return rc;

@@ -42,4 +42,26 @@ __device__ inline void dot2_step(float x, float y, float& s, float& c) {
     c += es + ep;
 }
 
+// Narrow FP64 to FP32 rounding to odd: a later round-to-nearest-even step to a
+// format with at least two fewer significand bits then equals one correct
+// rounding from FP64 (Boldo & Melquiond, IEEE Trans. Computers 57(4), 2008).
+__device__ inline float to_float_round_odd(double x) {
+    float f = (float)x;  // round to nearest even
+    if ((double)f != x && x == x) {
+        uint32_t u = __float_as_uint(f);
+        if (fabs((double)f) > fabs(x)) u -= 1;  // step back toward zero (also inf -> max finite)
+        u |= 1u;
+        f = __uint_as_float(u);
+    }
+    return f;
+}
+
+// FP32 -> bfloat16 bits, round to nearest even (NaN kept quiet).
+__device__ inline uint16_t float_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 }  // namespace dfjk

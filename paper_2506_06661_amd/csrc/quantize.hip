@@ -10,28 +10,11 @@
 // IEEE Trans. Computers 57(4), 2008); float carries 24 bits against 8 (bf16)
 // and 11 (fp16), and covers both formats' subnormal ranges.
 #include "internal.h"
+#include "numerics.h"
 
 namespace dfjk {
 
 namespace {
-
-__device__ inline float to_float_round_odd(double x) {
-    float f = (float)x;  // round to nearest even
-    if ((double)f != x && x == x) {
-        uint32_t u = __float_as_uint(f);
-        if (fabs((double)f) > fabs(x)) u -= 1;  // step back toward zero (also inf -> max finite)
-        u |= 1u;
-        f = __uint_as_float(u);
-    }
-    return f;
-}
-
-__device__ inline uint16_t float_to_bf16_rne(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
 
 __global__ void quantize_kernel(const double* __restrict__ src, void* __restrict__ dst, int dtype,
                                 int64_t n) {

@@ -222,6 +222,24 @@ int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
     return k_build_factored(h, ws.Cf, n, ws.sign, 1.0, K);
 }
 
+int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D) {
+    const int64_t n = h->nao;
+    if (n > kMaxEighN) {
+        set_error("dfjk_aufbau: nao=%lld above %d", (long long)n, kMaxEighN);
+        return DFJK_E_INVALID;
+    }
+    ScfWs ws;
+    int rc = scf_ws(h, h->scf_ready, ws);
+    if (rc) return rc;
+    const hipStream_t st = h->stream;
+    symmetrize_kernel<<<dim3((unsigned)cdiv(n * n, 256)), 256, 0, st>>>(F, n, ws.A);
+    DFJK_LAUNCH_CHECK("symmetrize_kernel");
+    if ((rc = eigh(st, ws.A, ws.V, (int)n, true, ws.work, ws.iwork, ws.w))) return rc;
+    if ((rc = eig_gather(st, ws.V, (int)n, ws.iwork, (int)nocc, ws.w, 0, C, nullptr))) return rc;
+    if (D) return dgemm(st, false, true, n, n, nocc, 2.0, C, nocc, C, nocc, 0.0, D, n);
+    return DFJK_OK;
+}
+
 int scf_reset(dfjk_ctx* h) {
     h->scf_iter = 0;
     h->scf_count = 0;

@@ -47,7 +47,7 @@ class Mol(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("diis_space", ctypes.c_int), ("conv_tol", ctypes.c_double),
                 ("conv_tol_grad", ctypes.c_double), ("max_cycle", ctypes.c_int),
-                ("compensated_j", ctypes.c_int)]
+                ("compensated_j", ctypes.c_int), ("k16", ctypes.c_int)]
 
 
 _lib = None
@@ -103,6 +103,8 @@ def lib():
             getattr(L, name).restype = i32
         L.dfjk_scf_step.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.POINTER(ScfInfo)]
         L.dfjk_scf_reset.argtypes = [vp]
+        L.dfjk_aufbau.argtypes = [vp, vp, i64, vp, vp]
+        L.dfjk_aufbau.restype = i32
         L.dfjk_tile_count.argtypes = [i32]
         L.dfjk_tile_info.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.dfjk_set_tile.argtypes = [vp, i32, i32]
@@ -176,6 +178,7 @@ def dfjk_workspace_bytes(h) -> int:
 
 
 DFJK_TILE_GEMM1 = 0
+DFJK_TILE_J_OUT = 1
 
 
 def dfjk_scf_step(h, H, D, Cocc, nocc: int, flags: int = 0, want_info: bool = True):
@@ -184,6 +187,10 @@ def dfjk_scf_step(h, H, D, Cocc, nocc: int, flags: int = 0, want_info: bool = Tr
     rc = lib().dfjk_scf_step(h, _ptr(H), _ptr(D), _ptr(Cocc), nocc, flags,
                              ctypes.byref(info) if want_info else None)
     return _check("dfjk_scf_step", rc), info
+
+
+def dfjk_aufbau(h, F, nocc: int, Cocc, D=None) -> int:
+    return _check("dfjk_aufbau", lib().dfjk_aufbau(h, _ptr(F), nocc, _ptr(Cocc), _ptr(D)))
 
 
 def dfjk_scf_reset(h) -> int:

@@ -1,0 +1,165 @@
+"""Learned initial guess: data from the plain SCF, training, and use.
+
+The paper's mean-field runs take any guess density (Sec. IV.A.1); the
+default accelerator is DIIS (Sec. IV.B).  This module drives the library:
+
+* ``run_scf``      -- DIIS SCF on the GPU through ``dfjk_scf_step`` from the
+                      core-Hamiltonian guess or a given density.
+* ``Trainer``      -- fits the perceptron (library kernels: forward, backward,
+                      Adam) to converged densities, as corrections of the
+                      core guess on the packed pairs.
+* ``guess_density``-- features -> network -> D0 = Dcore + correction.
+* ``solve``        -- SCF from the learned guess with the core guess as the
+                      fallback (non-finite D0, electron count off by more than
+                      25%, no convergence, or a converged energy different from
+                      a reference).
+
+Systems are passed in as arrays (H, packed B, positions R); nothing here
+draws random inputs except the seeded parameter initialisation, whose
+uniform numbers are supplied by the caller.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import dfjk as _d
+
+
+def core_guess(handle: _d.Handle, H: torch.Tensor, nocc: int):
+    """Aufbau on the core Hamiltonian (the library's eigensolver): (C, D)."""
+    nao = H.shape[0]
+    C = torch.empty((nao, nocc), dtype=torch.float64, device=H.device)
+    D = torch.empty((nao, nao), dtype=torch.float64, device=H.device)
+    _d.dfjk_aufbau(handle.h, H, nocc, C, D)
+    return C, D
+
+
+def run_scf(handle: _d.Handle, H: torch.Tensor, nocc: int, D0: torch.Tensor | None = None,
+            C0: torch.Tensor | None = None, max_iter: int = 100):
+    """DIIS SCF from D0 (K through C0 when given, else through D0's
+    eigen-factors on the first iteration).  Returns (records, D, C) with one
+    (e_tot, err_norm, converged) record per J/K build."""
+    nao = H.shape[0]
+    _d.dfjk_scf_reset(handle.h)
+    if D0 is None:
+        C0, D0 = core_guess(handle, H, nocc)
+    D = D0.clone().contiguous()
+    C = (C0.clone() if C0 is not None else torch.zeros((nao, nocc), dtype=torch.float64,
+                                                       device=H.device)).contiguous()
+    flags = _d.DFJK_SCF_C_VALID if C0 is not None else 0
+    recs = []
+    for _ in range(max_iter):
+        _, info = _d.dfjk_scf_step(handle.h, H, D, C, nocc, flags)
+        flags = _d.DFJK_SCF_C_VALID
+        recs.append((info.e_tot, info.err_norm, bool(info.converged)))
+        if info.converged or not math.isfinite(info.e_tot):
+            break
+    return recs, D, C
+
+
+def builds_to(recs, e_ref: float, tol: float = 1e-6):
+    """J/K builds until |E_k - E_ref| < tol, or None."""
+    for k, (e, _, _) in enumerate(recs):
+        if abs(e - e_ref) < tol:
+            return k + 1
+    return None
+
+
+def features(H: torch.Tensor, Dcore: torch.Tensor, R: torch.Tensor) -> torch.Tensor:
+    nao = H.shape[0]
+    X = torch.empty((nao * (nao + 1) // 2, 8), dtype=torch.float32, device=H.device)
+    _d.dfjk_guess_features(H, Dcore, R, nao, X)
+    return X
+
+
+def packed(M: torch.Tensor) -> torch.Tensor:
+    """Lower-triangle entries of a symmetric matrix in packed pair order."""
+    nao = M.shape[0]
+    r, c = torch.tril_indices(nao, nao, device=M.device)
+    return M[r, c]
+
+
+class Trainer:
+    """Mean-squared-error fit of the perceptron with Adam (library kernels)."""
+
+    def __init__(self, mlp: _d.MLP, init_uniform: np.ndarray):
+        """init_uniform: nparam uniforms in [0, 1) for Glorot initialisation
+        of the weight matrices (biases start at zero)."""
+        self.mlp = mlp
+        flat, o = [], 0
+        for s in mlp.shapes():
+            n = int(np.prod(s))
+            if len(s) == 2:  # weight matrix: Glorot-uniform
+                lim = math.sqrt(6.0 / (s[0] + s[1]))
+                flat.append((2.0 * init_uniform[o:o + n] - 1.0) * lim)
+            else:
+                flat.append(np.zeros(n))
+            o += n
+        mlp.set_params(np.concatenate(flat))
+
+    def fit(self, X: torch.Tensor, t: torch.Tensor, epochs: int, batch: int, lr: float,
+            order_uniform: np.ndarray | None = None, log=None):
+        """X (n x 8), t (n) on the device.  order_uniform: one uniform per row
+        and epoch for the shuffle (or None: fixed order)."""
+        n = X.shape[0]
+        loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+        hist = []
+        for ep in range(epochs):
+            if order_uniform is not None:
+                perm = torch.from_numpy(np.argsort(order_uniform[ep * n:(ep + 1) * n], kind="stable")).to(X.device)
+                Xe, te = X[perm].contiguous(), t[perm].contiguous()
+            else:
+                Xe, te = X, t
+            tot = 0.0
+            nb = 0
+            for b0 in range(0, n, batch):
+                xb, tb = Xe[b0:b0 + batch], te[b0:b0 + batch]
+                self.mlp.loss_grad(xb, tb, loss)
+                self.mlp.adam(lr)
+                tot += float(loss.item()) if (nb % 64 == 0) else 0.0
+                nb += 1
+            hist.append(tot)
+            if log:
+                log(f"epoch {ep + 1}/{epochs}")
+        return hist
+
+    def predict(self, X: torch.Tensor) -> torch.Tensor:
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        self.mlp.forward(X, y)
+        return y
+
+
+def guess_density(handle: _d.Handle, trainer: Trainer, H: torch.Tensor, R: torch.Tensor, nocc: int):
+    """D0 = Dcore + network correction on the packed pairs."""
+    _, Dc = core_guess(handle, H, nocc)
+    X = features(H, Dc, R)
+    y = trainer.predict(X)
+    D0 = torch.empty_like(Dc)
+    _d.dfjk_guess_assemble(y, Dc, H.shape[0], D0)
+    return D0
+
+
+def solve(handle: _d.Handle, trainer: Trainer, H: torch.Tensor, R: torch.Tensor, nocc: int,
+          e_ref: float | None = None, max_iter: int = 100, tol: float = 1e-6):
+    """SCF from the learned guess with the core guess as fallback.  Returns
+    a dict with the build count to |E - e_ref| < tol (including a fallback
+    run), whether the fallback ran, and the records."""
+    D0 = guess_density(handle, trainer, H, R, nocc)
+    ok = bool(torch.isfinite(D0).all().item())
+    if ok:
+        ne = float(torch.trace(D0).item())
+        ok = abs(ne - 2 * nocc) <= 0.25 * 2 * nocc
+    recs = run_scf(handle, H, nocc, D0=D0, max_iter=max_iter)[0] if ok else []
+    conv = bool(recs) and recs[-1][2]
+    if conv and e_ref is not None and abs(recs[-1][0] - e_ref) > tol:
+        conv = False
+    builds = len(recs) if not conv else (builds_to(recs, e_ref, tol) if e_ref is not None else len(recs))
+    if conv:
+        return {"builds": builds, "fallback": False, "records": recs}
+    fb = run_scf(handle, H, nocc, max_iter=max_iter)[0]
+    nb = builds_to(fb, e_ref, tol) if e_ref is not None else len(fb)
+    return {"builds": len(recs) + (nb if nb is not None else len(fb)), "fallback": True,
+            "records": recs + fb}

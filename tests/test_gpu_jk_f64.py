@@ -106,3 +106,16 @@ def test_every_gemm1_tile(pkg):
         pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_GEMM1, t)
         K = host(h.K(C=Cd))
         assert max_rel(K, K_ref) < TOL, (t, pkg.dfjk_tile_info(pkg.DFJK_TILE_GEMM1, t))
+
+
+def test_every_j_out_width(pkg):
+    """Each compiled J pass-2 column width gives the oracle's J."""
+    nao, naux, nocc = 300, 33, 5
+    R, B, C = system(nao, naux, nocc, 26)
+    D = 2 * C @ C.T
+    J_ref = oracle.J(B, nao, D)
+    h = pkg.Handle(dev(B), nao)
+    Dd = dev(D)
+    for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_J_OUT)):
+        pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_J_OUT, t)
+        assert max_rel(host(h.J(Dd)), J_ref) < TOL, t

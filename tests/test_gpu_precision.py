@@ -93,3 +93,28 @@ def test_reduced_J_K(pkg, dtype, nao, naux, nocc, seed, ld_pad):
             assert np.array_equal(K, K.T)
         h.close()
     print({k: f"{v:.2e}" for k, v in errs.items()})
+
+
+@pytest.mark.parametrize("dtype,bound", [(BF16, 5e-3), (F16, 1e-3)])
+@pytest.mark.parametrize("nao,naux,nocc,seed", [(64, 256, 16, 1), (300, 40, 37, 33), (129, 20, 40, 34)])
+def test_k16_exchange(pkg, dtype, bound, nao, naux, nocc, seed):
+    """K on the 16-bit matrix cores (dense 16-bit copy of B).  Reference: the
+    oracle on the dequantised B with C rounded once to the same format.  X is
+    rounded to 16 bits after FP32 accumulation, so by Cauchy-Schwarz
+    |dK_mn| <= 2 (u + nao u32) sqrt(K_mm K_nn) <= 2 (u + nao u32) max|K|
+    (u = 2^-9 bf16, 2^-12 fp16): asserted at 5e-3 and 1e-3."""
+    print(f"k16 dtype={dtype} nao={nao} naux={naux} nocc={nocc}", flush=True)
+    R, B, C = system(nao, naux, nocc, seed)
+    Bq = QUANT[dtype](B)
+    Cq = QUANT[dtype](C)
+    opts = pkg.dfjk.default_options()
+    opts.k16 = 1
+    h = pkg.Handle(gpu_quantize(pkg, B, dtype), nao, dtype=dtype, opts=opts)
+    K = host(h.K(C=dev(C)))
+    K_ref = oracle.K_C(Bq, nao, Cq)
+    err = max_rel(K, K_ref)
+    print(f"  k16 err vs rounded-input oracle {err:.2e}; vs FP64 {frob_rel(K, oracle.K_C(B, nao, C)):.2e}")
+    assert err < bound
+    assert np.array_equal(K, K.T)
+    K2 = host(h.K(C=dev(C)))  # the dense copy is made once and reused
+    assert np.array_equal(K, K2)
