@@ -259,9 +259,10 @@ def bench_c5(args):
     from paper_2506_06661_amd import guess
 
     cfg = synth.C5
+    b_scale = synth.C5_B_SCALE if args.b_scale is None else args.b_scale
 
     def system(seed):
-        R, B, H = synth.scf_system(seed, cfg)
+        R, B, H = synth.scf_system(seed, cfg, b_scale)
         return pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao), torch.from_numpy(H).cuda(), \
             torch.from_numpy(R).cuda()
 
@@ -291,7 +292,7 @@ def bench_c5(args):
            order_uniform=synth.uniform(2, synth.STREAM_MLP, X.shape[0] * args.epochs), log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - tt
-    core, learned, fb, fails = [], [], 0, 0
+    core, learned, proj, fb, fails = [], [], [], 0, 0
     for seed in range(2000, 2000 + args.n_test):
         h, H, R = system(seed)
         ref, _, _ = guess.run_scf(h, H, cfg.nocc)
@@ -304,8 +305,9 @@ def bench_c5(args):
         out = guess.solve(h, tr, H, R, cfg.nocc, e_ref=e_ref)
         learned.append(out["builds"])
         fb += out["fallback"]
+        proj.append(guess.solve(h, tr, H, R, cfg.nocc, e_ref=e_ref, projected=True)["builds"])
         h.close()
-    core, learned = np.array(core, float), np.array(learned, float)
+    core, learned, proj = np.array(core, float), np.array(learned, float), np.array(proj, float)
     res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
            "value": float(learned.mean()), "unit": "J/K builds to 1e-6 Eh (mean)", "n_gpus": 1,
            "steps": int(len(learned)), "warmup": 0, "ms_per_step": float(np.mean(scf_ms)),
@@ -313,10 +315,12 @@ def bench_c5(args):
            "data": "synthetic",
            "config": {"workload": f"learned guess: nao={cfg.nao}, naux={cfg.naux}, nocc={cfg.nocc}, "
                                   f"{args.n_train} training systems, {args.n_test} held out, "
-                                  f"B scaled by {synth.C5_B_SCALE}", "epochs": args.epochs},
+                                  f"B scaled by {b_scale}", "epochs": args.epochs, "b_scale": b_scale},
            "core_guess_builds_mean": float(core.mean()), "core_guess_builds_median": float(np.median(core)),
            "learned_builds_mean": float(learned.mean()), "learned_builds_median": float(np.median(learned)),
            "paired_mean_difference": float((learned - core).mean()),
+           "projected_builds_mean": float(proj.mean()),
+           "projected_paired_mean_difference": float((proj - core).mean()),
            "fallbacks": int(fb), "test_systems_not_converged_plain": int(fails),
            "train_systems_converged": int(nconv), "train_pairs": int(X.shape[0]),
            "train_seconds": train_s, "plain_scf_ms_mean": float(np.mean(scf_ms))}
@@ -335,6 +339,8 @@ def main():
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--b-scale", type=float, default=None,
+                    help="c5: scale of B in the SCF family (default: the generator's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--cpu-rows", type=int, default=1024,

@@ -30,8 +30,10 @@ int dots(hipStream_t st, const DotList& list, int nd, int64_t n, double* part, d
 size_t dots_part_elems(int nd);
 
 // Symmetric eigendecomposition by parallel cyclic Jacobi in one workgroup.
-// A (n x n) is overwritten; V (n x n) is set to the identity first when
-// v_identity, else it holds the basis the eigenvectors are expressed in.
+// A (n x n) is overwritten; V (n x n) holds a basis as ROWS (set to the
+// identity first when v_identity): on entry A must be expressed in that basis
+// (A = V F V^T); on exit row k of V is the eigenvector of F with eigenvalue
+// A[k][k].
 // work: >= n + 2 doubles; iwork: >= n + 2 ints (iwork[0] = sweeps used,
 // iwork[1 + r] = index of the r-th smallest eigenvalue); w: n eigenvalues in
 // ascending order.

@@ -106,12 +106,19 @@ __global__ void dots_finish(const double* __restrict__ part, int nd, double* __r
 
 // ---------------------------------------------------------------- Jacobi
 // Parallel cyclic Jacobi on a symmetric n x n matrix A (overwritten; the
-// eigenvalues end on its diagonal), accumulating V (n x n, starts as the
-// caller's basis; columns become eigenvectors in that basis).  Each sweep
-// visits every pair (p,q) once in the round-robin (circle) order: n-1 rounds
-// of n/2 disjoint pairs (a dummy index when n is odd).  Rotations follow the
-// symmetric Schur step of Golub & Van Loan (Matrix Computations, 8.5.2).
+// eigenvalues end on its diagonal).  Vt (n x n) holds the basis as ROWS: it
+// starts as the caller's basis (rows orthonormal) and its row k ends as the
+// eigenvector of diagonal entry k.  Each sweep visits every pair (p,q) once in
+// the round-robin (circle) order: n-1 rounds of n/2 disjoint pairs (a dummy
+// index when n is odd).  Rotations follow the symmetric Schur step of Golub &
+// Van Loan (Matrix Computations, 8.5.2): with J[p][p] = J[q][q] = c,
+// J[p][q] = s, J[q][p] = -s, a round applies A <- J^T A J and Vt <- J^T Vt for
+// all of its pairs at once.  Because every index is in one pair, the new
+// entries of rows (p, q) and columns (a, b) depend only on the old 2x2 block
+// A[{p,q}][{a,b}], so one thread updates each such block in place and a round
+// needs a single barrier.
 constexpr int JT = 1024;
+constexpr int kJacobiShN = 128;  // A in LDS up to 128 x 128 doubles (128 KB)
 
 __device__ inline void pair_of(int r, int k, int m, int& p, int& q) {
     // circle method on m (even) players; player m-1 fixed
@@ -129,11 +136,24 @@ __device__ inline void pair_of(int r, int k, int m, int& p, int& q) {
     }
 }
 
-__global__ __launch_bounds__(JT) void jacobi_kernel(double* __restrict__ A, double* __restrict__ V,
+// y = J^T x on the pair (p, q): (c x_p - s x_q, s x_p + c x_q)
+__device__ inline void rot(double c, double s, double xp, double xq, double& yp, double& yq) {
+    yp = c * xp - s * xq;
+    yq = s * xp + c * xq;
+}
+
+template <bool SH>
+__global__ __launch_bounds__(JT) void jacobi_kernel(double* __restrict__ Ag, double* __restrict__ Vt,
                                                      int n, double* __restrict__ cs, int max_sweeps,
                                                      double tol, int* __restrict__ sweeps_done) {
+    extern __shared__ double smem[];
     __shared__ double red[JT / 64];
     __shared__ int stop;
+    double* __restrict__ A = SH ? smem : Ag;
+    if (SH) {
+        for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += JT) A[e] = Ag[e];
+        __syncthreads();
+    }
     const int m = n + (n & 1);
     const int half = m / 2;
     double* cc = cs;
@@ -169,7 +189,7 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(double* __restrict__ A, doub
         __syncthreads();
         if (stop) break;
         for (int r = 0; r < m - 1; ++r) {
-            // rotation of each pair from the current A
+            // rotation of each pair from the current A (dummy pairs: c = 1, s = 0)
             for (int k = threadIdx.x; k < half; k += JT) {
                 int p, q;
                 pair_of(r, k, m, p, q);
@@ -188,44 +208,53 @@ __global__ __launch_bounds__(JT) void jacobi_kernel(double* __restrict__ A, doub
                 ss[k] = s;
             }
             __syncthreads();
-            // columns: A <- A J, V <- V J
-            for (int64_t e = threadIdx.x; e < (int64_t)half * n; e += JT) {
-                const int k = (int)(e / n), i = (int)(e % n);
-                int p, q;
+            // A <- J^T A J by 2x2 blocks (row pair k, column pair kk)
+            for (int64_t e = threadIdx.x; e < (int64_t)half * half; e += JT) {
+                const int k = (int)(e / half), kk = (int)(e % half);
+                int p, q, a, b;
                 pair_of(r, k, m, p, q);
-                if (q >= n) continue;
-                const double c = cc[k], s = ss[k];
-                const double aip = A[(int64_t)i * n + p], aiq = A[(int64_t)i * n + q];
-                A[(int64_t)i * n + p] = c * aip - s * aiq;
-                A[(int64_t)i * n + q] = s * aip + c * aiq;
-                const double vip = V[(int64_t)i * n + p], viq = V[(int64_t)i * n + q];
-                V[(int64_t)i * n + p] = c * vip - s * viq;
-                V[(int64_t)i * n + q] = s * vip + c * viq;
+                pair_of(r, kk, m, a, b);
+                const double c = cc[k], s = ss[k], c2 = cc[kk], s2 = ss[kk];
+                const bool qv = q < n, bv = b < n;
+                // old block
+                const double apa = A[(int64_t)p * n + a];
+                const double apb = bv ? A[(int64_t)p * n + b] : 0.0;
+                const double aqa = qv ? A[(int64_t)q * n + a] : 0.0;
+                const double aqb = (qv && bv) ? A[(int64_t)q * n + b] : 0.0;
+                // rows: (p, q) <- J^T
+                double rpa, rqa, rpb, rqb;
+                rot(c, s, apa, aqa, rpa, rqa);
+                rot(c, s, apb, aqb, rpb, rqb);
+                // columns: (a, b) <- J
+                double npa, npb, nqa, nqb;
+                rot(c2, s2, rpa, rpb, npa, npb);
+                rot(c2, s2, rqa, rqb, nqa, nqb);
+                if (k == kk) {  // the rotated pair's own block: off-diagonal is zero by construction
+                    npb = 0.0;
+                    nqa = 0.0;
+                }
+                A[(int64_t)p * n + a] = npa;
+                if (bv) A[(int64_t)p * n + b] = npb;
+                if (qv) A[(int64_t)q * n + a] = nqa;
+                if (qv && bv) A[(int64_t)q * n + b] = nqb;
             }
-            __syncthreads();
-            // rows: A <- J^T A
+            // Vt <- J^T Vt (row rotations; contiguous rows)
             for (int64_t e = threadIdx.x; e < (int64_t)half * n; e += JT) {
                 const int k = (int)(e / n), j = (int)(e % n);
                 int p, q;
                 pair_of(r, k, m, p, q);
                 if (q >= n) continue;
                 const double c = cc[k], s = ss[k];
-                const double apj = A[(int64_t)p * n + j], aqj = A[(int64_t)q * n + j];
-                A[(int64_t)p * n + j] = c * apj - s * aqj;
-                A[(int64_t)q * n + j] = s * apj + c * aqj;
-            }
-            __syncthreads();
-            // the rotated pair's off-diagonal element is zero by construction
-            for (int k = threadIdx.x; k < half; k += JT) {
-                int p, q;
-                pair_of(r, k, m, p, q);
-                if (q < n) {
-                    A[(int64_t)p * n + q] = 0.0;
-                    A[(int64_t)q * n + p] = 0.0;
-                }
+                double yp, yq;
+                rot(c, s, Vt[(int64_t)p * n + j], Vt[(int64_t)q * n + j], yp, yq);
+                Vt[(int64_t)p * n + j] = yp;
+                Vt[(int64_t)q * n + j] = yq;
             }
             __syncthreads();
         }
+    }
+    if (SH) {
+        for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += JT) Ag[e] = A[e];
     }
     if (threadIdx.x == 0) *sweeps_done = sweep;
 }
@@ -245,8 +274,8 @@ __global__ void eig_rank(const double* __restrict__ A, int n, int* __restrict__ 
     w[rank] = ai;
 }
 
-// out[r][c] = scale(c) * V[r][pos_of_rank[c]] for c < ncol (row-major n x ncol)
-__global__ void gather_cols(const double* __restrict__ V, int n, const int* __restrict__ pos_of_rank,
+// out[r][c] = scale(c) * Vt[pos_of_rank[c]][r] for c < ncol (row-major n x ncol)
+__global__ void gather_cols(const double* __restrict__ Vt, int n, const int* __restrict__ pos_of_rank,
                             int ncol, const double* __restrict__ w, int mode, double* __restrict__ out,
                             double* __restrict__ sign) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,7 +283,7 @@ __global__ void gather_cols(const double* __restrict__ V, int n, const int* __re
     const int r = (int)(e / ncol), c = (int)(e % ncol);
     double f = 1.0;
     if (mode == 1) f = sqrt(fabs(w[c]));  // signed square-root factor
-    out[e] = f * V[(int64_t)r * n + pos_of_rank[c]];
+    out[e] = f * Vt[(int64_t)pos_of_rank[c] * n + r];
     if (sign && r == 0) sign[c] = w[c] < 0.0 ? -1.0 : 1.0;
 }
 
@@ -317,9 +346,23 @@ int eigh(hipStream_t st, double* A, double* V, int n, bool v_identity, double* w
         set_identity<<<dim3((unsigned)cdiv((int64_t)n * n, 256)), 256, 0, st>>>(V, n);
         DFJK_LAUNCH_CHECK("set_identity");
     }
-    // stop when the off-diagonal norm is below n * eps of the matrix norm
-    const double tol = (double)n * 2.220446049250313e-16;
-    jacobi_kernel<<<1, JT, 0, st>>>(A, V, n, work, 40, tol, iwork);
+    // stop when the off-diagonal norm is below 1e-13 of the matrix norm
+    // (convergence is quadratic, so the sweep after reaching ~1e-7 lands at
+    // the rounding floor; a bound at n*eps can sit below that floor and is
+    // then never met)
+    if (n <= kJacobiShN) {
+        const size_t bytes = sizeof(double) * (size_t)n * n;
+        static bool attr_set = false;
+        if (!attr_set) {
+            DFJK_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&jacobi_kernel<true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(sizeof(double) * kJacobiShN * kJacobiShN)));
+            attr_set = true;
+        }
+        jacobi_kernel<true><<<1, JT, bytes, st>>>(A, V, n, work, 40, 1e-13, iwork);
+    } else {
+        jacobi_kernel<false><<<1, JT, 0, st>>>(A, V, n, work, 40, 1e-13, iwork);
+    }
     DFJK_LAUNCH_CHECK("jacobi_kernel");
     eig_rank<<<dim3((unsigned)cdiv(n, 256)), 256, 0, st>>>(A, n, iwork + 1, w);
     DFJK_LAUNCH_CHECK("eig_rank");

@@ -91,6 +91,7 @@ struct dfjk_ctx {
     // SCF state (scf.hip): iterations done, DIIS vectors stored
     int scf_iter = 0, scf_count = 0;
     bool scf_ready = false;
+    bool scf_v_warm = false;  // eigensolver buffer V holds the last SCF eigenbasis
 
     dfjk::Prof prof;
 };

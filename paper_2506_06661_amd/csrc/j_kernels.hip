@@ -577,7 +577,9 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out) {
                                                                        rho_out);
     DFJK_LAUNCH_CHECK("j_rho_finish");
 
-    const int t = h->jout_tile >= 0 && h->jout_tile < kNumJOut ? h->jout_tile : 0;
+    // default width 2048 columns (sweep at nao=1024, naux=4096 FP64: total J
+    // 5.33 / 5.27 / 5.29 / 5.32 ms for 1024 / 2048 / 4096 / 8192 columns)
+    const int t = h->jout_tile >= 0 && h->jout_tile < kNumJOut ? h->jout_tile : 1;
     const int U = kJOutU[t];
     int64_t splits;
     j_out_geometry(h, U, &splits);

@@ -174,6 +174,7 @@ static int scf_ws(dfjk_ctx* h, bool scf, ScfWs& ws) {
         opart = take(dots_part_elems(kMaxDots)), oen = take(16), oep = take(1),
         orec = take(sizeof(ScfRecord) / sizeof(double) + 1);
     }
+    if (need * sizeof(double) > h->eig.bytes) h->scf_v_warm = false;  // fresh buffer
     int rc = h->eig.ensure(need * sizeof(double));
     if (rc) return rc;
     double* base = static_cast<double*>(h->eig.ptr);
@@ -205,6 +206,7 @@ static int scf_ws(dfjk_ctx* h, bool scf, ScfWs& ws) {
 
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
     const int64_t n = h->nao;
+    h->scf_v_warm = false;  // the eigensolver buffer is reused below
     if (n > kMaxEighN) {
         set_error("K from a density needs nao <= %d (got %lld); pass Cocc", kMaxEighN, (long long)n);
         return DFJK_E_INVALID;
@@ -224,6 +226,7 @@ int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
 
 int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D) {
     const int64_t n = h->nao;
+    h->scf_v_warm = false;
     if (n > kMaxEighN) {
         set_error("dfjk_aufbau: nao=%lld above %d", (long long)n, kMaxEighN);
         return DFJK_E_INVALID;
@@ -241,6 +244,7 @@ int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D) {
 }
 
 int scf_reset(dfjk_ctx* h) {
+    h->scf_v_warm = false;
     h->scf_iter = 0;
     h->scf_count = 0;
     return DFJK_OK;
@@ -309,10 +313,18 @@ int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, i
         DFJK_LAUNCH_CHECK("diis_combine");
     }
 
-    // aufbau on the extrapolated Fock matrix
+    // aufbau on the extrapolated Fock matrix; from the second iteration on the
+    // Jacobi sweeps start in the previous eigenbasis (rows of V): V F V^T is
+    // then nearly diagonal and needs few sweeps; V accumulates the rotations
+    const bool warm = h->scf_v_warm;
+    if (warm) {
+        if ((rc = dgemm(st, false, true, n, n, n, 1.0, ws.Fx, n, ws.V, n, 0.0, ws.G, n))) return rc;
+        if ((rc = dgemm(st, false, false, n, n, n, 1.0, ws.V, n, ws.G, n, 0.0, ws.Fx, n))) return rc;
+    }
     symmetrize_kernel<<<g2, 256, 0, st>>>(ws.Fx, n, ws.A);
     DFJK_LAUNCH_CHECK("symmetrize_kernel");
-    if ((rc = eigh(st, ws.A, ws.V, (int)n, true, ws.work, ws.iwork, ws.w))) return rc;
+    if ((rc = eigh(st, ws.A, ws.V, (int)n, !warm, ws.work, ws.iwork, ws.w))) return rc;
+    h->scf_v_warm = true;
     if ((rc = eig_gather(st, ws.V, (int)n, ws.iwork, (int)nocc, ws.w, 0, C, nullptr))) return rc;
     if ((rc = dgemm(st, false, true, n, n, nocc, 2.0, C, nocc, C, nocc, 0.0, D, n))) return rc;
 

@@ -142,17 +142,32 @@ def guess_density(handle: _d.Handle, trainer: Trainer, H: torch.Tensor, R: torch
     return D0
 
 
+def project(handle: _d.Handle, D0: torch.Tensor, nocc: int):
+    """Closest idempotent density of rank nocc: D = 2 C C^T with C the
+    eigenvectors of the nocc largest eigenvalues of D0."""
+    nao = D0.shape[0]
+    C = torch.empty((nao, nocc), dtype=torch.float64, device=D0.device)
+    D = torch.empty_like(D0)
+    _d.dfjk_aufbau(handle.h, (-D0).contiguous(), nocc, C, D)
+    return C, D
+
+
 def solve(handle: _d.Handle, trainer: Trainer, H: torch.Tensor, R: torch.Tensor, nocc: int,
-          e_ref: float | None = None, max_iter: int = 100, tol: float = 1e-6):
-    """SCF from the learned guess with the core guess as fallback.  Returns
-    a dict with the build count to |E - e_ref| < tol (including a fallback
-    run), whether the fallback ran, and the records."""
+          e_ref: float | None = None, max_iter: int = 100, tol: float = 1e-6, projected: bool = False):
+    """SCF from the learned guess with the core guess as fallback.  With
+    `projected`, the guess is first replaced by the closest idempotent density
+    of rank nocc (then the first exchange goes through C).  Returns a dict
+    with the build count to |E - e_ref| < tol (including a fallback run),
+    whether the fallback ran, and the records."""
     D0 = guess_density(handle, trainer, H, R, nocc)
     ok = bool(torch.isfinite(D0).all().item())
     if ok:
         ne = float(torch.trace(D0).item())
         ok = abs(ne - 2 * nocc) <= 0.25 * 2 * nocc
-    recs = run_scf(handle, H, nocc, D0=D0, max_iter=max_iter)[0] if ok else []
+    C0 = None
+    if ok and projected:
+        C0, D0 = project(handle, D0, nocc)
+    recs = run_scf(handle, H, nocc, D0=D0, C0=C0, max_iter=max_iter)[0] if ok else []
     conv = bool(recs) and recs[-1][2]
     if conv and e_ref is not None and abs(recs[-1][0] - e_ref) > tol:
         conv = False

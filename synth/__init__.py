@@ -271,9 +271,9 @@ def small_system(nao: int, naux: int, nocc: int, seed: int):
 C5_B_SCALE = 0.005
 
 
-def scf_system(seed: int, cfg: Config = C5):
+def scf_system(seed: int, cfg: Config = C5, b_scale: float = C5_B_SCALE):
     """(R, B, H) of one member of the SCF family."""
     R = positions_c5(seed)
-    B = B_full(seed, R, cfg.naux) * C5_B_SCALE
+    B = B_full(seed, R, cfg.naux) * b_scale
     H = core_hamiltonian(seed, R)
     return R, B, H

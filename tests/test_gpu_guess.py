@@ -50,7 +50,7 @@ def test_learned_guess_pipeline(pkg):
     order = synth.uniform(2, synth.STREAM_MLP, X.shape[0] * 3)
     hist = tr.fit(X, t, epochs=3, batch=65536, lr=1e-3, order_uniform=order)
     print("loss samples", hist)
-    core, learned, fallbacks = [], [], 0
+    core, learned, projected, fallbacks = [], [], [], 0
     for seed in range(2000, 2010):
         h, H, R = system(pkg, seed)
         ref, _, _ = guess.run_scf(h, H, cfg.nocc)
@@ -63,9 +63,12 @@ def test_learned_guess_pipeline(pkg):
         fallbacks += out["fallback"]
         final = out["records"][-1]
         assert final[2] and abs(final[0] - e_ref) < 1e-6
+        outp = guess.solve(h, tr, H, R, cfg.nocc, e_ref=e_ref, projected=True)
+        projected.append(outp["builds"])
+        assert outp["records"][-1][2] and abs(outp["records"][-1][0] - e_ref) < 1e-6
         h.close()
     print(f"builds to 1e-6 Eh: core {np.mean(core):.2f}, learned {np.mean(learned):.2f}, "
-          f"fallbacks {fallbacks}/{len(learned)}")
+          f"projected {np.mean(projected):.2f}, fallbacks {fallbacks}/{len(learned)}")
     assert len(learned) >= 8
 
 
