@@ -143,6 +143,26 @@ def bench_c3(args):
                      "k_gemm1_frac_of_f32_peak": g1_flops / ph["K_gemm1"] / 1e9 / PEAK["f32"],
                      "j_frac_of_hbm": jb / ph["J"] / 1e6 / PEAK["hbm_gbs"]}
         h.close()
+        # the same build with K on the 16-bit matrix cores (dense 16-bit copy of B)
+        opts = pkg.dfjk.default_options()
+        opts.k16 = 1
+        h16 = pkg.Handle(buf, cfg.nao, dtype=code, opts=opts)
+        Kt = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        pkg.dfjk_build_K(h16.h, Cd, cfg.nocc, None, Kt)  # makes the dense copy
+        torch.cuda.synchronize()
+        first_ms = (time.perf_counter() - tc) * 1e3
+        r16 = time_steps(pkg, h16, Dd, Cd, cfg, args.steps, args.warmup)
+        p16 = r16["phase_ms"]
+        peak16 = PEAK[name]
+        out[name]["k16"] = {"k_tflops": (g1_flops + sy_flops) / p16["K"] / 1e9, "ms_per_step": r16["ms_per_step"],
+                            "phase_ms": p16, "first_call_ms_incl_dense_copy": first_ms,
+                            "dense_copy_gb": h16.workspace_bytes() / 1e9,
+                            "k_gemm1_frac_of_16bit_peak": g1_flops / p16["K_gemm1"] / 1e9 / peak16,
+                            "k_syrk_frac_of_16bit_peak": sy_flops / p16["K_syrk"] / 1e9 / peak16}
+        h16.close()
+        del Kt
         log(name, out[name])
     res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
            "value": out["bf16"]["k_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -150,7 +170,8 @@ def bench_c3(args):
            "scaling": "weak", "vs_baseline": None, "dtype": "f32 (B stored bf16/f16)", "data": "synthetic",
            "config": {"workload": f"DF J/K build: nao={cfg.nao}, naux={cfg.naux}, nocc={cfg.nocc}, packed B "
                                   f"stored BF16 and FP16 (34 GB each), J FP64 accumulation, K on FP32 "
-                                  f"matrix cores", "nao": cfg.nao, "naux": cfg.naux, "nocc": cfg.nocc},
+                                  f"matrix cores (k16: on 16-bit matrix cores)", "nao": cfg.nao,
+                      "naux": cfg.naux, "nocc": cfg.nocc},
            "bf16": out["bf16"], "f16": out["f16"]}
     print(json.dumps(res), flush=True)
 

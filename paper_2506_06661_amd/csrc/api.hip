@@ -221,15 +221,27 @@ int dfjk_tile_count(int kernel) {
     clear_error();
     if (kernel == DFJK_TILE_GEMM1) return k_tile_count();
     if (kernel == DFJK_TILE_J_OUT) return j_out_count();
+    if (kernel == DFJK_TILE_K16) return 3;
     set_error("dfjk_tile_count: unknown kernel %d", kernel);
     return DFJK_E_INVALID;
 }
 
 int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
     clear_error();
-    if ((kernel != DFJK_TILE_GEMM1 && kernel != DFJK_TILE_J_OUT) || !p0 || !p1) {
+    if ((kernel != DFJK_TILE_GEMM1 && kernel != DFJK_TILE_J_OUT && kernel != DFJK_TILE_K16) || !p0 ||
+        !p1) {
         set_error("dfjk_tile_info: unknown kernel or null output");
         return DFJK_E_INVALID;
+    }
+    if (kernel == DFJK_TILE_K16) {
+        static const int cols[] = {64, 128, 208};
+        if (index < 0 || index >= 3) {
+            set_error("dfjk_tile_info: index %d out of range", index);
+            return DFJK_E_INVALID;
+        }
+        *p0 = cols[index];
+        *p1 = 128;
+        return DFJK_OK;
     }
     if (kernel == DFJK_TILE_J_OUT) {
         static const int widths[] = {2, 4, 8, 16};
@@ -252,15 +264,18 @@ int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
     clear_error();
     if (int rc = check_handle(h)) return rc;
     const int count = kernel == DFJK_TILE_GEMM1 ? k_tile_count()
-                      : kernel == DFJK_TILE_J_OUT ? j_out_count() : 0;
+                      : kernel == DFJK_TILE_J_OUT ? j_out_count()
+                      : kernel == DFJK_TILE_K16 ? 3 : 0;
     if (count == 0 || index < -1 || index >= count) {
         set_error("dfjk_set_tile: kernel %d / index %d invalid", kernel, index);
         return DFJK_E_INVALID;
     }
     if (kernel == DFJK_TILE_GEMM1)
         h->g1_tile = index;
-    else
+    else if (kernel == DFJK_TILE_J_OUT)
         h->jout_tile = index;
+    else
+        h->k16_tile = index;
     return DFJK_OK;
 }
 

@@ -87,6 +87,7 @@ struct dfjk_ctx {
 
     int g1_tile = -1;       // GEMM1 tile index (-1: heuristic)
     int jout_tile = -1;     // J pass-2 column width index (-1: default)
+    int k16_tile = -1;      // 16-bit GEMM1 column tile index (-1: default)
 
     // SCF state (scf.hip): iterations done, DIIS vectors stored
     int scf_iter = 0, scf_count = 0;

@@ -388,7 +388,9 @@ __global__ __launch_bounds__(kThreads) void j_out_red(const TB* __restrict__ B, 
 template <typename TB, int ACC>
 int j_build_red_t(dfjk_ctx* h, double* J, double* rho_out) {
     constexpr int V = Elem<TB>::V;
-    constexpr int R = 8;
+    // rows per workgroup in pass 1: each FP64 (or FP32 hi/lo) weight is loaded
+    // once per R rows, so 16-bit B uses more rows to keep that traffic small
+    constexpr int R = sizeof(TB) == 2 ? 16 : 8;
     const TB* B = static_cast<const TB*>(h->B);
     double* dt = static_cast<double*>(h->dt.ptr);
     float* dhi = reinterpret_cast<float*>(dt + h->npair);

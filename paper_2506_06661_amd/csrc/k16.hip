@@ -104,21 +104,74 @@ __global__ void c_transpose(const double* __restrict__ C, int64_t nao, int64_t n
 }
 
 // ---------------------------------------------------------------- GEMM1
-// Workgroup: 128 rows mu (4 waves x 32) x 16*NI columns i, one P.
+// Workgroup: 128 rows mu (4 waves x 32) x 16*NI columns i, one P.  The
+// contraction runs in 64-deep chunks (two matrix-core steps); the next
+// chunk's 16-byte pieces are loaded into registers while the current chunk is
+// multiplied from the other LDS buffer.
+constexpr int KC16 = 64;
+constexpr int LROW64 = KC16 + 8;  // 72 halves = 144 bytes per LDS row
+
+template <typename H, int NI>
+struct G16Stage {
+    u4 a[(128 * KC16 / 8 + kT - 1) / kT];        // 1024 pieces / 256 threads = 4
+    u4 b[(16 * NI * KC16 / 8 + kT - 1) / kT];    // 128*NI pieces
+};
+
+template <typename H, int NI>
+__device__ inline void g16_load(G16Stage<H, NI>& st, const H* __restrict__ A, int64_t ldd,
+                                const H* __restrict__ Ct, int64_t ncp, int64_t mu0, int64_t i0,
+                                int64_t k0, int tid) {
+    constexpr int NA = 128 * KC16 / 8, NB = 16 * NI * KC16 / 8;
+#pragma unroll
+    for (int j = 0; j < (NA + kT - 1) / kT; ++j) {
+        const int e = tid + j * kT;
+        const int r = e >> 3, q = e & 7;
+        const int64_t mu = mu0 + r;
+        st.a[j] = (e < NA && mu < ldd && k0 + 8 * q < ldd)
+                      ? *reinterpret_cast<const u4*>(A + mu * ldd + k0 + 8 * q)
+                      : u4{0u, 0u, 0u, 0u};
+    }
+#pragma unroll
+    for (int j = 0; j < (NB + kT - 1) / kT; ++j) {
+        const int e = tid + j * kT;
+        const int r = e >> 3, q = e & 7;
+        const int64_t i = i0 + r;
+        st.b[j] = (e < NB && i < ncp && k0 + 8 * q < ldd)
+                      ? *reinterpret_cast<const u4*>(Ct + i * ldd + k0 + 8 * q)
+                      : u4{0u, 0u, 0u, 0u};
+    }
+}
+
+template <typename H, int NI>
+__device__ inline void g16_store(const G16Stage<H, NI>& st, H (*sA)[LROW64], H (*sB)[LROW64], int tid) {
+    constexpr int NA = 128 * KC16 / 8, NB = 16 * NI * KC16 / 8;
+#pragma unroll
+    for (int j = 0; j < (NA + kT - 1) / kT; ++j) {
+        const int e = tid + j * kT;
+        if (e < NA) *reinterpret_cast<u4*>(&sA[e >> 3][8 * (e & 7)]) = st.a[j];
+    }
+#pragma unroll
+    for (int j = 0; j < (NB + kT - 1) / kT; ++j) {
+        const int e = tid + j * kT;
+        if (e < NB) *reinterpret_cast<u4*>(&sB[e >> 3][8 * (e & 7)]) = st.b[j];
+    }
+}
+
+__device__ inline int64_t xcd_lid(int64_t hw, int64_t nblk) {
+    constexpr int64_t NX = 8;
+    const int64_t per = nblk / NX, rem = nblk % NX, x = hw % NX, q = hw / NX;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
 template <typename H, int NI>
 __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ldd, int64_t nao,
                                              const H* __restrict__ Ct, int64_t ncol, int64_t ncp,
                                              H* __restrict__ X, int64_t nib, int64_t nmb, int64_t nblk) {
     constexpr int BI = 16 * NI, BM = 128;
-    __shared__ H sA[BM][LROW];
-    __shared__ H sB[BI][LROW];
+    __shared__ H sA[2][BM][LROW64];
+    __shared__ H sB[2][BI][LROW64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t lid = [&] {
-        constexpr int64_t NX = 8;
-        const int64_t per = nblk / NX, rem = nblk % NX, x = blockIdx.x % NX, q = blockIdx.x / NX;
-        const int64_t start = x * per + (x < rem ? x : rem);
-        return start + q;
-    }();
+    const int64_t lid = xcd_lid(blockIdx.x, nblk);
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, mu0 = mb * BM;
     const H* A = Bd + P * ldd * ldd;
@@ -127,35 +180,30 @@ __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ld
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NI; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    const int64_t nk = ldd / KS;
+    const int64_t nk = ldd / KC16 + (ldd % KC16 ? 1 : 0);
+    G16Stage<H, NI> st;
+    g16_load<H, NI>(st, A, ldd, Ct, ncp, mu0, i0, 0, tid);
+    g16_store<H, NI>(st, sA[0], sB[0], tid);
+    __syncthreads();
     for (int64_t kc = 0; kc < nk; ++kc) {
-        const int64_t k0 = kc * KS;
-        // A: 128 rows x 32 halves = 512 16-byte pieces; B: BI rows x 32 = 4*BI pieces
-        for (int e = tid; e < BM * 4; e += kT) {
-            const int r = e >> 2, q = e & 3;
-            const int64_t mu = mu0 + r;
-            u4 v = u4{0u, 0u, 0u, 0u};
-            if (mu < ldd) v = *reinterpret_cast<const u4*>(A + mu * ldd + k0 + 8 * q);
-            *reinterpret_cast<u4*>(&sA[r][8 * q]) = v;
-        }
-        for (int e = tid; e < BI * 4; e += kT) {
-            const int r = e >> 2, q = e & 3;
-            const int64_t i = i0 + r;
-            u4 v = u4{0u, 0u, 0u, 0u};
-            if (i < ncp) v = *reinterpret_cast<const u4*>(Ct + i * ldd + k0 + 8 * q);
-            *reinterpret_cast<u4*>(&sB[r][8 * q]) = v;
-        }
-        __syncthreads();
-        u4 a[2];
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nk;
+        if (more) g16_load<H, NI>(st, A, ldd, Ct, ncp, mu0, i0, (kc + 1) * KC16, tid);
 #pragma unroll
-        for (int t = 0; t < 2; ++t)
-            a[t] = *reinterpret_cast<const u4*>(&sA[wave * 32 + t * 16 + (lane & 15)][8 * (lane >> 4)]);
+        for (int ks = 0; ks < KC16 / KS; ++ks) {
+            u4 a[2];
 #pragma unroll
-        for (int n = 0; n < NI; ++n) {
-            const u4 b = *reinterpret_cast<const u4*>(&sB[n * 16 + (lane & 15)][8 * (lane >> 4)]);
+            for (int t = 0; t < 2; ++t)
+                a[t] = *reinterpret_cast<const u4*>(
+                    &sA[buf][wave * 32 + t * 16 + (lane & 15)][ks * KS + 8 * (lane >> 4)]);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) acc[t][n] = Mma16<H>::step(a[t], b, acc[t][n]);
+            for (int n = 0; n < NI; ++n) {
+                const u4 b = *reinterpret_cast<const u4*>(&sB[buf][n * 16 + (lane & 15)][ks * KS + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) acc[t][n] = Mma16<H>::step(a[t], b, acc[t][n]);
+            }
         }
+        if (more) g16_store<H, NI>(st, sA[buf ^ 1], sB[buf ^ 1], tid);
         __syncthreads();
     }
 #pragma unroll
@@ -173,20 +221,46 @@ __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ld
 
 // ---------------------------------------------------------------- GEMM2
 // Lower tile (I >= J) of 128 x 128 of K; 2 x 2 waves of 64 x 64; the
-// contraction over (P, i) runs in 32-wide steps inside each P.
+// contraction over (P, i) runs in 32-wide steps inside each P, staged two
+// steps at a time with the next pair prefetched into registers.
+struct S16Stage {
+    u4 a[2], b[2];  // 2 x 128 rows x 32 halves = 1024 pieces / 256 threads... per operand 512: 2 each
+};
+
+template <typename H>
+__device__ inline void s16_load(S16Stage& st, const H* __restrict__ X, int64_t nao, int64_t ncp,
+                                int64_t P, int64_t k0, int64_t mu0, int64_t nu0, int tid) {
+    const H* XP = X + P * nao * ncp;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int e = tid + j * kT;  // 512 pieces: row e>>2, quarter e&3
+        const int r = e >> 2, q = e & 3;
+        st.a[j] = (mu0 + r < nao) ? *reinterpret_cast<const u4*>(XP + (mu0 + r) * ncp + k0 + 8 * q)
+                                  : u4{0u, 0u, 0u, 0u};
+        st.b[j] = (nu0 + r < nao) ? *reinterpret_cast<const u4*>(XP + (nu0 + r) * ncp + k0 + 8 * q)
+                                  : u4{0u, 0u, 0u, 0u};
+    }
+}
+
+template <typename H>
+__device__ inline void s16_store(const S16Stage& st, H (*sA)[LROW], H (*sB)[LROW], int tid) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int e = tid + j * kT;
+        *reinterpret_cast<u4*>(&sA[e >> 2][8 * (e & 3)]) = st.a[j];
+        *reinterpret_cast<u4*>(&sB[e >> 2][8 * (e & 3)]) = st.b[j];
+    }
+}
+
 template <typename H>
 __global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t nao, int64_t ncp,
                                                int64_t naux, int64_t pchunk, int64_t ntl, int64_t nblk,
                                                float* __restrict__ part) {
-    __shared__ H sA[128][LROW];
-    __shared__ H sB[128][LROW];
+    __shared__ H sA[2][128][LROW];
+    __shared__ H sB[2][128][LROW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int64_t lid = [&] {
-        constexpr int64_t NX = 8;
-        const int64_t per = nblk / NX, rem = nblk % NX, x = blockIdx.x % NX, q = blockIdx.x / NX;
-        return x * per + (x < rem ? x : rem) + q;
-    }();
+    const int64_t lid = xcd_lid(blockIdx.x, nblk);
     const int64_t t = lid % ntl, s = lid / ntl;
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
@@ -200,29 +274,30 @@ __global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t n
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     const int64_t nks = ncp / KS;
-    for (int64_t P = P0; P < P1; ++P) {
-        const H* XP = X + P * nao * ncp;
-        for (int64_t kc = 0; kc < nks; ++kc) {
-            const int64_t k0 = kc * KS;
-            for (int e = tid; e < 128 * 4; e += kT) {
-                const int r = e >> 2, q = e & 3;
-                u4 va = u4{0u, 0u, 0u, 0u}, vb = u4{0u, 0u, 0u, 0u};
-                if (mu0 + r < nao) va = *reinterpret_cast<const u4*>(XP + (mu0 + r) * ncp + k0 + 8 * q);
-                if (nu0 + r < nao) vb = *reinterpret_cast<const u4*>(XP + (nu0 + r) * ncp + k0 + 8 * q);
-                *reinterpret_cast<u4*>(&sA[r][8 * q]) = va;
-                *reinterpret_cast<u4*>(&sB[r][8 * q]) = vb;
+    const int64_t nsteps = (P1 > P0 ? P1 - P0 : 0) * nks;  // (P, 32-wide step) in order
+    if (nsteps > 0) {
+        S16Stage st;
+        s16_load<H>(st, X, nao, ncp, P0, 0, mu0, nu0, tid);
+        s16_store<H>(st, sA[0], sB[0], tid);
+        __syncthreads();
+        for (int64_t step = 0; step < nsteps; ++step) {
+            const int buf = step & 1;
+            const bool more = step + 1 < nsteps;
+            if (more) {
+                const int64_t nx = step + 1;
+                s16_load<H>(st, X, nao, ncp, P0 + nx / nks, (nx % nks) * KS, mu0, nu0, tid);
             }
-            __syncthreads();
             u4 a[4], b[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                a[q] = *reinterpret_cast<const u4*>(&sA[wm * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
-                b[q] = *reinterpret_cast<const u4*>(&sB[wn * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+                a[q] = *reinterpret_cast<const u4*>(&sA[buf][wm * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+                b[q] = *reinterpret_cast<const u4*>(&sB[buf][wn * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
             }
 #pragma unroll
             for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = Mma16<H>::step(a[ti], b[tj], acc[ti][tj]);
+            if (more) s16_store<H>(st, sA[buf ^ 1], sB[buf ^ 1], tid);
             __syncthreads();
         }
     }
@@ -264,6 +339,7 @@ __global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ pa
 template <typename H, int NI>
 void launch_g1(hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
                int64_t ncp, H* X, int64_t naux) {
+
     const int64_t nib = cdiv(ncp, 16 * NI), nmb = cdiv(nao, 128);
     const int64_t nblk = nib * nmb * naux;
     g1_16<H, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
@@ -273,7 +349,7 @@ template <typename H>
 int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     const hipStream_t st = h->stream;
     const int64_t nao = h->nao, naux = h->naux;
-    const int64_t ldd = cdiv(nao, KS) * KS;
+    const int64_t ldd = cdiv(nao, KC16) * KC16;  // dense row length: 64-deep chunks
     const int64_t ncp = cdiv(ncol, KS) * KS;
     int rc;
     if (!h->dense_ready) {
@@ -293,8 +369,18 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     c_transpose<H><<<dim3((unsigned)cdiv(ncp * ldd, 256)), 256, 0, st>>>(C, nao, ncol, ncp, ldd, Ct);
     DFJK_LAUNCH_CHECK("c_transpose");
     h->prof.begin(PH_K_GEMM1, st);
-    if (ncp <= 64) launch_g1<H, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
-    else launch_g1<H, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    // column tile: 64, 128 or 208 occupied orbitals (the handle's choice, else
+    // 128 unless nocc fits in 64: on MI355X at nao=2048, nocc=400 BF16 the
+    // 128-wide tile ran at 585 TFLOP/s against 444 for 208 (one wave per SIMD)
+    // and 440 for 64, although it pads 400 to 512)
+    int t = h->k16_tile;
+    if (t < 0) t = ncp <= 64 ? 0 : 1;
+    if (t == 2)
+        launch_g1<H, 13>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    else if (t == 1)
+        launch_g1<H, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    else
+        launch_g1<H, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
     const int64_t nt = cdiv(nao, 128), ntl = nt * (nt + 1) / 2;

@@ -425,12 +425,14 @@ __global__ void to_f32(const double* __restrict__ x, int64_t n, float* __restric
 // read of the B tile (weight 1/2 of a padded column block), among the tiles
 // that keep two waves per SIMD (FP64 sweep on MI355X, nao=1024, nocc=200:
 // (7,1) 43.8 TFLOP/s, (5,2) 43.5, (13,1) 40.4, (1,2) 32.6).
-int pick_g1_tile(int64_t ncol) {
+// FP32 compute (FP32/BF16/FP16 storage) allows at most 5 accumulator tiles
+// (sweep at nocc=200: (5,1) 66.2 TFLOP/s, (7,1) 63.1, (4,2) 59.1, (1,2) 50.3).
+int pick_g1_tile(int64_t ncol, bool f32 = false) {
     int best = 0;
     double best_cost = 1e300;
     for (int t = 0; t < kNumG1Tiles; ++t) {
         const int ni = kG1Tiles[t].ni, wm = kG1Tiles[t].wm;
-        if (ni * wm > 7) continue;  // larger accumulator sets leave one wave per SIMD
+        if (ni * wm > (f32 ? 5 : 7)) continue;  // larger accumulator sets leave one wave per SIMD
         const double padded = (double)(cdiv(ncol, 16 * ni) * 16 * ni);
         const double cost = padded * (1.0 + 0.5 / ni);
         if (cost < best_cost) {
@@ -451,7 +453,8 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
 
     h->prof.begin(PH_K, h->stream);
     h->prof.begin(PH_K_GEMM1, h->stream);
-    const int tile = h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles ? h->g1_tile : pick_g1_tile(ncol);
+    const int tile = h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles ? h->g1_tile
+                                                                  : pick_g1_tile(ncol, sizeof(T) == 4);
     rc = kG1Tiles[tile].by_dtype[h->dtype](h, C, ncol, X, ldx);
     h->prof.end(PH_K_GEMM1, h->stream);
     if (rc) return rc;
@@ -563,7 +566,7 @@ int k_batch_gemm1(hipStream_t st, int dtype, int tile, const MolDesc* mols, cons
     return kKbTiles[tile](st, dtype, mols, pl);
 }
 
-int pick_tile(int64_t ncol) { return pick_g1_tile(ncol); }
+int pick_tile(int64_t ncol) { return pick_g1_tile(ncol, true); }
 
 int tile_nb(int tile, int64_t nao, int64_t ncol, int64_t* nib, int64_t* nmb) {
     if (tile < 0 || tile >= kNumG1Tiles) return DFJK_E_INVALID;

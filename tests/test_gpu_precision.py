@@ -118,3 +118,6 @@ def test_k16_exchange(pkg, dtype, bound, nao, naux, nocc, seed):
     assert np.array_equal(K, K.T)
     K2 = host(h.K(C=dev(C)))  # the dense copy is made once and reused
     assert np.array_equal(K, K2)
+    for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_K16)):  # every GEMM1 tile
+        pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_K16, t)
+        assert max_rel(host(h.K(C=dev(C))), K_ref) < bound, t
