@@ -494,6 +494,12 @@ def main():
                       "traffic": traffic.get("j_out_" + args.dtype)},
         },
     }
+    res["measured_mfma_ceiling_tflops"] = {
+        "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
+        "bf16_16x16x32": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}
+    res["roofline"]["frac_of_measured_ceiling"] = (
+        res["roofline"]["achieved"] / res["measured_mfma_ceiling_tflops"]["f64_16x16x4" if args.dtype == "f64"
+                                                                         else "f32_16x16x4"])
     h.close()
     if args.dtype == "f64":
         # the same workload with B stored in FP32 (one RNE step from FP64)

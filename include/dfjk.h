@@ -275,6 +275,13 @@ int dfjk_guess_features(const double* H_dev, const double* Dcore_dev, const doub
 int dfjk_guess_assemble(const float* y_dev, const double* Dcore_dev, int64_t nao, double* D_dev,
                         void* stream);
 
+/*
+ * Sustained matrix-core rate (TFLOP/s) of v_mfma_f64_16x16x4f64 (DFJK_F64),
+ * v_mfma_f32_16x16x4f32 (DFJK_F32) or v_mfma_f32_16x16x32_bf16 (DFJK_BF16),
+ * measured with register-only kernels on the current device (waits).
+ */
+int dfjk_probe_mfma(int dtype, double* tflops);
+
 /* Device workspace currently held by the handle, in bytes. */
 int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes);
 

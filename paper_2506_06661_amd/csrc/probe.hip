@@ -1,0 +1,103 @@
+// Sustained matrix-core rate, measured with register-only kernels (no memory
+// traffic): every wavefront repeats independent 16x16 steps on eight
+// accumulators, eight wavefronts per SIMD.  Used to state how far the
+// exchange kernels sit from what the matrix cores sustain, beside the
+// published peaks.
+#include "internal.h"
+#include "mma.h"
+
+namespace dfjk {
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kAcc = 8;
+
+__global__ __launch_bounds__(256) void probe_f64(double* out, int iters) {
+    v4d acc[kAcc];
+    for (int t = 0; t < kAcc; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    const double a = threadIdx.x * 1e-3, b = 1.0 + threadIdx.x * 1e-4;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int t = 0; t < kAcc; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+    double s = 0.0;
+    for (int t = 0; t < kAcc; ++t) s += acc[t][0] + acc[t][3];
+    if (s == -1.0) out[0] = s;  // keeps the work; never true for these inputs
+}
+
+__global__ __launch_bounds__(256) void probe_f32(double* out, int iters) {
+    v4f acc[kAcc];
+    for (int t = 0; t < kAcc; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float a = threadIdx.x * 1e-3f, b = 1.0f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int t = 0; t < kAcc; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+    float s = 0.f;
+    for (int t = 0; t < kAcc; ++t) s += acc[t][0];
+    if (s == -1.f) out[0] = s;
+}
+
+__global__ __launch_bounds__(256) void probe_bf16(double* out, int iters) {
+    v4f acc[kAcc];
+    for (int t = 0; t < kAcc; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    v8bf a, b;
+    for (int j = 0; j < 8; ++j) {
+        a[j] = (__bf16)(threadIdx.x * 1e-3f);
+        b[j] = (__bf16)1.0f;
+    }
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int t = 0; t < kAcc; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+    float s = 0.f;
+    for (int t = 0; t < kAcc; ++t) s += acc[t][0];
+    if (s == -1.f) out[0] = s;
+}
+
+}  // namespace
+}  // namespace dfjk
+
+using namespace dfjk;
+
+extern "C" int dfjk_probe_mfma(int dtype, double* tflops) {
+    clear_error();
+    if (!tflops || (dtype != DFJK_F64 && dtype != DFJK_F32 && dtype != DFJK_BF16)) {
+        set_error("dfjk_probe_mfma: dtype must be DFJK_F64, DFJK_F32 or DFJK_BF16");
+        return DFJK_E_INVALID;
+    }
+    int ndev = 0, dev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error("dfjk_probe_mfma: no HIP device available");
+        return DFJK_E_NO_DEVICE;
+    }
+    DFJK_HIP_TRY(hipGetDevice(&dev));
+    int cus = 0;
+    DFJK_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    double* out = nullptr;
+    DFJK_HIP_TRY(hipMalloc(&out, 64));
+    hipEvent_t e0, e1;
+    DFJK_HIP_TRY(hipEventCreate(&e0));
+    DFJK_HIP_TRY(hipEventCreate(&e1));
+    const int blocks = cus * 8, iters = 2000;  // 8 workgroups of 4 waves per CU
+    const double per = dtype == DFJK_BF16 ? 16384.0 : 2048.0;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms the clocks
+        (void)hipEventRecord(e0, nullptr);
+        if (dtype == DFJK_F64) probe_f64<<<blocks, 256>>>(out, iters);
+        else if (dtype == DFJK_F32) probe_f32<<<blocks, 256>>>(out, iters);
+        else probe_bf16<<<blocks, 256>>>(out, iters);
+        (void)hipEventRecord(e1, nullptr);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    const hipError_t le = hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (le != hipSuccess) {
+        set_error("dfjk_probe_mfma: launch failed: %s", hipGetErrorString(le));
+        return DFJK_E_HIP;
+    }
+    *tflops = per * kAcc * iters * (double)blocks * 4.0 / (ms * 1e9);
+    return DFJK_OK;
+}

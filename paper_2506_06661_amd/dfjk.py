@@ -103,6 +103,8 @@ def lib():
             getattr(L, name).restype = i32
         L.dfjk_scf_step.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.POINTER(ScfInfo)]
         L.dfjk_scf_reset.argtypes = [vp]
+        L.dfjk_probe_mfma.argtypes = [i32, ctypes.POINTER(dbl)]
+        L.dfjk_probe_mfma.restype = i32
         L.dfjk_aufbau.argtypes = [vp, vp, i64, vp, vp]
         L.dfjk_aufbau.restype = i32
         L.dfjk_tile_count.argtypes = [i32]
@@ -192,6 +194,13 @@ def dfjk_scf_step(h, H, D, Cocc, nocc: int, flags: int = 0, want_info: bool = Tr
 
 def dfjk_aufbau(h, F, nocc: int, Cocc, D=None) -> int:
     return _check("dfjk_aufbau", lib().dfjk_aufbau(h, _ptr(F), nocc, _ptr(Cocc), _ptr(D)))
+
+
+def dfjk_probe_mfma(dtype: int) -> float:
+    """Sustained matrix-core TFLOP/s for the dtype's instruction."""
+    out = ctypes.c_double()
+    _check("dfjk_probe_mfma", lib().dfjk_probe_mfma(dtype, ctypes.byref(out)))
+    return out.value
 
 
 def dfjk_scf_reset(h) -> int:
