@@ -172,6 +172,15 @@ def quantize_f32(x: np.ndarray) -> np.ndarray:
 
 def _quantize(x, emin, mant, emax):
     x = np.asarray(x, np.float64)
+    out = np.empty(x.shape, np.float64)
+    xf, of = x.reshape(-1), out.reshape(-1)
+    step = 1 << 16  # elementwise; pieces only keep the temporaries in cache
+    for s in range(0, xf.size, step):
+        of[s:s + step] = _quantize_piece(xf[s:s + step], emin, mant, emax)
+    return out
+
+
+def _quantize_piece(x, emin, mant, emax):
     _, e = np.frexp(x)  # x = f * 2^e, 0.5 <= |f| < 1, so the leading bit has weight 2^(e-1)
     lead = np.maximum(e - 1, emin)
     quantum = np.ldexp(1.0, lead - mant)
