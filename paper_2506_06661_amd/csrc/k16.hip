@@ -26,6 +26,8 @@ typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
 constexpr int KS = 32;         // contraction chunk (one matrix-core step)
+constexpr int64_t kMaxSum16 = 16384;  // longest FP32 running sum in the SYRK
+constexpr int kFin16 = 16;            // SYRK finish: workgroups per output tile
 constexpr int LROW = KS + 8;   // LDS row: 32 halves + 8 of padding (80 bytes)
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -316,20 +318,26 @@ __global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t n
 
 // K = scale * sum_s part[s][t] over the lower triangle, mirrored (diagonal
 // tiles use m >= n only, so K is exactly symmetric).
+// grid: kFin16 blocks per lower tile, each adding up a contiguous slice of it
 __global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ part, int64_t nsplit,
                                                      int64_t ntl, int64_t nao, double scale,
                                                      double* __restrict__ K) {
-    const int64_t t = blockIdx.x;
+    constexpr int per = 128 * 128 / kFin16;
+    const int64_t t = blockIdx.x / kFin16;
+    const int sub = (int)(blockIdx.x % kFin16);
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int64_t J = t - I * (I + 1) / 2;
-    for (int e = threadIdx.x; e < 128 * 128; e += kT) {
+    const int64_t stride = ntl * (int64_t)(128 * 128);
+    for (int e = sub * per + (int)threadIdx.x; e < (sub + 1) * per; e += kT) {
         const int m = e / 128, n = e % 128;
         const int64_t mu = I * 128 + m, nu = J * 128 + n;
         if (mu >= nao || nu >= nao || (I == J && m < n)) continue;
+        const float* p = part + t * (int64_t)(128 * 128) + e;
         double v = 0.0;
-        for (int64_t s = 0; s < nsplit; ++s) v += (double)part[(s * ntl + t) * (int64_t)(128 * 128) + e];
+#pragma unroll 8
+        for (int64_t s = 0; s < nsplit; ++s) v += (double)p[s * stride];  // fixed order
         v *= scale;
         K[mu * nao + nu] = v;
         K[nu * nao + mu] = v;
@@ -384,7 +392,10 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
     const int64_t nt = cdiv(nao, 128), ntl = nt * (nt + 1) / 2;
+    // about 2048 workgroups, and no FP32 running sum longer than kMaxSum16
+    // terms (the split partials are added in FP64)
     int64_t nsplit = cdiv(2048, ntl);
+    if (nsplit < cdiv(naux * ncp, kMaxSum16)) nsplit = cdiv(naux * ncp, kMaxSum16);
     if (nsplit > naux) nsplit = naux;
     const int64_t pchunk = cdiv(naux, nsplit);
     nsplit = cdiv(naux, pchunk);
@@ -396,7 +407,7 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     h->prof.end(PH_K_SYRK, st);
     DFJK_LAUNCH_CHECK("syrk_16");
     h->prof.begin(PH_K_FINISH, st);
-    syrk16_finish<<<dim3((unsigned)ntl), kT, 0, st>>>(part, nsplit, ntl, nao, scale, K);
+    syrk16_finish<<<dim3((unsigned)(ntl * kFin16)), kT, 0, st>>>(part, nsplit, ntl, nao, scale, K);
     h->prof.end(PH_K_FINISH, st);
     h->prof.end(PH_K, st);
     DFJK_LAUNCH_CHECK("syrk16_finish");

@@ -26,6 +26,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int KC = 16;      // contraction chunk held in LDS
 constexpr int SY_T = 128;   // SYRK output tile
+constexpr int64_t kMaxSum32 = 16384;  // longest FP32 running sum in the SYRK
+constexpr int kFinSub = 16;           // SYRK finish: workgroups per output tile
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -355,31 +357,38 @@ __global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int6
 // K[mu][nu] = K[nu][mu] = scale * sum_s partial[s][t][m][n] over the lower
 // triangle (on diagonal tiles only m >= n is used, so K is exactly symmetric).
 template <typename T>
-__device__ inline void k_syrk_finish_body(int64_t t, const T* __restrict__ part, int64_t nsplit,
-                                          int64_t ntl, int64_t nao, double scale,
+__device__ inline void k_syrk_finish_body(int64_t t, int e0, int e1, const T* __restrict__ part,
+                                          int64_t nsplit, int64_t ntl, int64_t nao, double scale,
                                           double* __restrict__ K) {
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int64_t J = t - I * (I + 1) / 2;
-    for (int e = threadIdx.x; e < SY_T * SY_T; e += kThreads) {
+    const int64_t stride = ntl * (int64_t)(SY_T * SY_T);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += kThreads) {
         const int m = e / SY_T, n = e % SY_T;
         const int64_t mu = I * SY_T + m, nu = J * SY_T + n;
         if (mu >= nao || nu >= nao) continue;
         if (I == J && m < n) continue;
+        const T* p = part + t * (int64_t)(SY_T * SY_T) + e;
         double v = 0.0;
-        for (int64_t s = 0; s < nsplit; ++s) v += (double)part[(s * ntl + t) * (int64_t)(SY_T * SY_T) + e];
+#pragma unroll 8
+        for (int64_t s = 0; s < nsplit; ++s) v += (double)p[s * stride];  // fixed order
         v *= scale;
         K[mu * nao + nu] = v;
         K[nu * nao + mu] = v;
     }
 }
 
+// grid: kFinSub blocks per lower tile, each adding up a contiguous slice of it
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ part, int64_t nsplit,
                                                            int64_t ntl, int64_t nao, double scale,
                                                            double* __restrict__ K) {
-    k_syrk_finish_body<T>(blockIdx.x, part, nsplit, ntl, nao, scale, K);
+    constexpr int per = SY_T * SY_T / kFinSub;
+    const int sub = (int)(blockIdx.x % kFinSub);
+    k_syrk_finish_body<T>(blockIdx.x / kFinSub, sub * per, (sub + 1) * per, part, nsplit, ntl, nao, scale,
+                          K);
 }
 
 template <typename T, typename TS, int NI, int WM>
@@ -461,7 +470,10 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
 
     const int64_t nt = cdiv(h->nao, SY_T);
     const int64_t ntl = nt * (nt + 1) / 2;
+    // about 2048 workgroups, and for FP32 no running sum longer than
+    // kMaxSum32 terms (the split partials are added in FP64)
     int64_t nsplit = cdiv(2048, ntl);
+    if (sizeof(T) == 4 && nsplit < cdiv(nrows, kMaxSum32)) nsplit = cdiv(nrows, kMaxSum32);
     const int64_t max_split = cdiv(nrows, 256);
     if (nsplit > max_split) nsplit = max_split;
     if (nsplit < 1) nsplit = 1;
@@ -475,7 +487,8 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
     h->prof.end(PH_K_SYRK, h->stream);
     DFJK_LAUNCH_CHECK("k_syrk");
     h->prof.begin(PH_K_FINISH, h->stream);
-    k_syrk_finish<T><<<dim3((unsigned)ntl), kThreads, 0, h->stream>>>(part, nsplit, ntl, h->nao, scale, K);
+    k_syrk_finish<T><<<dim3((unsigned)(ntl * kFinSub)), kThreads, 0, h->stream>>>(part, nsplit, ntl, h->nao,
+                                                                                   scale, K);
     h->prof.end(PH_K_FINISH, h->stream);
     h->prof.end(PH_K, h->stream);
     DFJK_LAUNCH_CHECK("k_syrk_finish");
@@ -511,7 +524,7 @@ __global__ __launch_bounds__(kThreads) void kb_kernel(int kind, const MolDesc* _
                                d.kpart);
             break;
         case BP_KFIN:
-            k_syrk_finish_body<float>(lid, d.kpart, d.nsplit, d.ntl, d.nao, 2.0, d.K);
+            k_syrk_finish_body<float>(lid, 0, SY_T * SY_T, d.kpart, d.nsplit, d.ntl, d.nao, 2.0, d.K);
             break;
         default:
             break;
