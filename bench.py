@@ -348,15 +348,88 @@ def bench_c5(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_c5mp(args):
+    """Mixed-precision SCF on the SCF family (nao=128, naux=512, nocc=24):
+    J/K from B stored in BF16 or FP16 until |FD - DF|_F < 1e-4, then from the
+    FP64 B; J/K builds to 1e-6 Eh of the plain FP64 SCF on n_test systems."""
+    import torch
+
+    import paper_2506_06661_amd as pkg
+    import synth
+    from paper_2506_06661_amd import guess
+
+    cfg = synth.C5
+    b_scale = synth.C5_B_SCALE if args.b_scale is None else args.b_scale
+    rows = {"plain": [], "bf16": [], "f16": []}
+    fails = 0
+    for seed in range(2000, 2000 + args.n_test):
+        R, B, H = synth.scf_system(seed, cfg, b_scale)
+        Bd = torch.from_numpy(B).cuda()
+        Hd = torch.from_numpy(H).cuda()
+        h64 = pkg.Handle(Bd, cfg.nao)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref, _, _ = guess.run_scf(h64, Hd, cfg.nocc)
+        t_plain = (time.perf_counter() - t0) * 1e3
+        if not ref[-1][2]:
+            fails += 1
+            h64.close()
+            continue
+        e_ref = ref[-1][0]
+        rows["plain"].append((guess.builds_to(ref, e_ref), 0, t_plain, 0.0, 0.0))
+        for name, code, tdt in [("bf16", pkg.DFJK_BF16, torch.bfloat16), ("f16", pkg.DFJK_F16, torch.float16)]:
+            Bq = torch.empty(Bd.shape, dtype=tdt, device="cuda")
+            pkg.dfjk_quantize(Bd, Bq, code, Bd.numel())
+            hq = pkg.Handle(Bq, cfg.nao, dtype=code)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs, _, _ = guess.run_scf_mixed(hq, h64, Hd, cfg.nocc)
+            ms = (time.perf_counter() - t0) * 1e3
+            nlow = sum(1 for r in recs if r[3])
+            n = guess.builds_to(recs, e_ref)
+            low_err = [r[0] for r in recs if r[3]][-1] - e_ref
+            rows[name].append((n if n is not None else float("nan"), nlow, ms, abs(recs[-1][0] - e_ref),
+                               low_err))
+            hq.close()
+        h64.close()
+        if (seed - 2000) % 50 == 0:
+            log(f"  system {seed - 2000 + 1}/{args.n_test}")
+    out = {}
+    for name, r in rows.items():
+        a = np.array(r, float)
+        out[name] = {"builds_to_1e-6_mean": float(np.nanmean(a[:, 0])),
+                     "builds_to_1e-6_median": float(np.nanmedian(a[:, 0])),
+                     "not_reached": int(np.isnan(a[:, 0]).sum()),
+                     "reduced_builds_mean": float(a[:, 1].mean()), "scf_ms_mean": float(a[:, 2].mean())}
+        if name != "plain":
+            out[name].update({"final_abs_err_max_Eh": float(a[:, 3].max()),
+                              "reduced_phase_err_at_switch_median_Eh": float(np.median(a[:, 4])),
+                              "reduced_phase_abs_err_at_switch_max_Eh": float(np.abs(a[:, 4]).max()),
+                              "paired_builds_difference_mean": float(np.nanmean(a[:, 0] - np.array(
+                                  rows["plain"], float)[:, 0]))})
+    res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
+           "value": out["bf16"]["builds_to_1e-6_mean"], "unit": "J/K builds to 1e-6 Eh (mean, BF16 then FP64)",
+           "n_gpus": 1, "steps": len(rows["plain"]), "warmup": 0, "ms_per_step": out["bf16"]["scf_ms_mean"],
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 SCF; J/K from bf16/f16 B, then f64 B", "data": "synthetic",
+           "config": {"workload": f"mixed-precision SCF: nao={cfg.nao}, naux={cfg.naux}, nocc={cfg.nocc}, "
+                                  f"{args.n_test} systems, B scaled by {b_scale}, switch at |FD-DF| < 1e-4",
+                      "b_scale": b_scale},
+           "plain": out["plain"], "bf16": out["bf16"], "f16": out["f16"],
+           "plain_not_converged": fails}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5mp"],
                     help="c2: nao=1024 FP64 (+FP32) single builds (default); c3: nao=2048 BF16/FP16; "
-                         "c4: 256-molecule batch; c5: learned-guess SCF experiment")
+                         "c4: 256-molecule batch; c5: learned-guess SCF experiment; "
+                         "c5mp: mixed-precision SCF")
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -396,6 +469,8 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    if args.workload == "c5mp":
+        return bench_c5mp(args)
     cfg = synth.C2
     t0 = time.time()
     R = synth.positions(cfg)

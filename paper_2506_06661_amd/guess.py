@@ -5,6 +5,9 @@ default accelerator is DIIS (Sec. IV.B).  This module drives the library:
 
 * ``run_scf``      -- DIIS SCF on the GPU through ``dfjk_scf_step`` from the
                       core-Hamiltonian guess or a given density.
+* ``run_scf_mixed``-- the same SCF with J/K from B stored at reduced
+                      precision until the commutator norm is small, then
+                      from the FP64 B.
 * ``Trainer``      -- fits the perceptron (library kernels: forward, backward,
                       Adam) to converged densities, as corrections of the
                       core guess on the packed pairs.
@@ -60,10 +63,40 @@ def run_scf(handle: _d.Handle, H: torch.Tensor, nocc: int, D0: torch.Tensor | No
     return recs, D, C
 
 
+def run_scf_mixed(h_low: _d.Handle, h64: _d.Handle, H: torch.Tensor, nocc: int, switch: float = 1e-4,
+                  max_iter: int = 100):
+    """SCF that builds J/K from B stored at reduced precision (h_low) until
+    the commutator norm |FD - DF|_F falls below `switch` (or that SCF
+    converges), then from the FP64 B (h64) with a fresh DIIS history,
+    continuing from the same density and orbitals.  Both handles describe the
+    same system.  Returns (records, D, C); each record is (e_tot, err_norm,
+    converged, reduced) with `reduced` True for builds from h_low."""
+    _d.dfjk_scf_reset(h_low.h)
+    _d.dfjk_scf_reset(h64.h)
+    C, D = core_guess(h64, H, nocc)
+    flags = _d.DFJK_SCF_C_VALID
+    recs = []
+    h, low = h_low, True
+    for _ in range(max_iter):
+        _, info = _d.dfjk_scf_step(h.h, H, D, C, nocc, flags)
+        recs.append((info.e_tot, info.err_norm, bool(info.converged) and not low, low))
+        if not math.isfinite(info.e_tot):
+            break
+        if low and (info.err_norm < switch or info.converged):
+            h, low = h64, False
+        elif not low and info.converged:
+            break
+    return recs, D, C
+
+
 def builds_to(recs, e_ref: float, tol: float = 1e-6):
-    """J/K builds until |E_k - E_ref| < tol, or None."""
-    for k, (e, _, _) in enumerate(recs):
-        if abs(e - e_ref) < tol:
+    """J/K builds until |E_k - E_ref| < tol, or None.  Builds from B stored
+    at reduced precision (a fourth record field that is True) do not count as
+    reaching it: their energies are not FP64 energies of the system."""
+    for k, rec in enumerate(recs):
+        if len(rec) > 3 and rec[3]:
+            continue
+        if abs(rec[0] - e_ref) < tol:
             return k + 1
     return None
 

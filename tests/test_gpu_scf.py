@@ -103,3 +103,36 @@ def test_scf_from_nonidempotent_guess(pkg):
         assert abs(recs[k][0] - ref["E"][k]) <= TOL * abs(ref["E"][k]), k
     if ref["converged"]:
         assert recs[-1][2] and abs(recs[-1][0] - ref["E"][-1]) < 1e-8
+
+
+@pytest.mark.parametrize("dtype", [2, 3])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_mixed_precision_scf(pkg, dtype, seed):
+    """J/K from B stored in BF16 (2) or FP16 (3) until |FD - DF|_F < 1e-4,
+    then from the FP64 B: the SCF ends at the energy of the plain FP64 SCF
+    (converged at 1e-9 Eh), so within 1e-6 Eh of it."""
+    from paper_2506_06661_amd import guess
+    cfg = synth.C5
+    print(f"mixed-precision SCF dtype={dtype} seed={seed}", flush=True)
+    R, B, H = synth.scf_system(seed, cfg)
+    Bd = dev(B)
+    h64 = pkg.Handle(Bd, cfg.nao)
+    Bq = torch.empty(Bd.shape, dtype={2: torch.bfloat16, 3: torch.float16}[dtype], device="cuda")
+    pkg.dfjk_quantize(Bd, Bq, dtype, Bd.numel())
+    hq = pkg.Handle(Bq, cfg.nao, dtype=dtype)
+    Hd = dev(H)
+    ref, _, _ = guess.run_scf(h64, Hd, cfg.nocc)
+    assert ref[-1][2]
+    e_ref = ref[-1][0]
+    recs, D, _ = guess.run_scf_mixed(hq, h64, Hd, cfg.nocc)
+    low = [r for r in recs if r[3]]
+    assert low and not recs[-1][3] and recs[-1][2]
+    assert abs(recs[-1][0] - e_ref) < 1e-6
+    n = guess.builds_to(recs, e_ref)
+    assert n is not None and n > len(low)
+    Dh = host(D)
+    assert abs(np.trace(Dh) - 2 * cfg.nocc) < 1e-9
+    print(f"  plain {guess.builds_to(ref, e_ref)} builds; mixed {len(low)} reduced + "
+          f"{n - len(low)} FP64 to 1e-6 Eh; reduced-phase energy error at switch {low[-1][0] - e_ref:.2e} Eh")
+    hq.close()
+    h64.close()
