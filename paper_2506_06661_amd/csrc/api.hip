@@ -221,7 +221,7 @@ int dfjk_tile_count(int kernel) {
     clear_error();
     if (kernel == DFJK_TILE_GEMM1) return k_tile_count();
     if (kernel == DFJK_TILE_J_OUT) return j_out_count();
-    if (kernel == DFJK_TILE_K16) return 3;
+    if (kernel == DFJK_TILE_K16) return k16_tile_count();
     set_error("dfjk_tile_count: unknown kernel %d", kernel);
     return DFJK_E_INVALID;
 }
@@ -234,13 +234,10 @@ int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
         return DFJK_E_INVALID;
     }
     if (kernel == DFJK_TILE_K16) {
-        static const int cols[] = {64, 128, 208};
-        if (index < 0 || index >= 3) {
+        if (k16_tile_info(index, p0, p1) != DFJK_OK) {
             set_error("dfjk_tile_info: index %d out of range", index);
             return DFJK_E_INVALID;
         }
-        *p0 = cols[index];
-        *p1 = 128;
         return DFJK_OK;
     }
     if (kernel == DFJK_TILE_J_OUT) {
@@ -265,7 +262,7 @@ int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
     if (int rc = check_handle(h)) return rc;
     const int count = kernel == DFJK_TILE_GEMM1 ? k_tile_count()
                       : kernel == DFJK_TILE_J_OUT ? j_out_count()
-                      : kernel == DFJK_TILE_K16 ? 3 : 0;
+                      : kernel == DFJK_TILE_K16 ? k16_tile_count() : 0;
     if (count == 0 || index < -1 || index >= count) {
         set_error("dfjk_set_tile: kernel %d / index %d invalid", kernel, index);
         return DFJK_E_INVALID;

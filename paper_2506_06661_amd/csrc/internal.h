@@ -115,6 +115,8 @@ int scf_reset(dfjk_ctx* h);
 int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D);
 int k_tile_count();
 int k_tile_info(int t, int* ni, int* wm);
+int k16_tile_count();
+int k16_tile_info(int t, int* cols, int* rows);
 
 // Batched builds (batch.hip drives; j_kernels.hip / k_kernels.hip launch).
 // One descriptor per molecule; all pointers are device pointers.

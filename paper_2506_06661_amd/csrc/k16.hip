@@ -28,7 +28,12 @@ constexpr int kT = 256;
 constexpr int KS = 32;         // contraction chunk (one matrix-core step)
 constexpr int64_t kMaxSum16 = 16384;  // longest FP32 running sum in the SYRK
 constexpr int kFin16 = 16;            // SYRK finish: workgroups per output tile
-constexpr int LROW = KS + 8;   // LDS row: 32 halves + 8 of padding (80 bytes)
+// SYRK LDS rows: one 32-wide step, 4 pieces of 16 bytes, piece p of row r
+// kept at p ^ ((r >> 1) & 3): conflict-free for the operand reads (16
+// consecutive rows, one piece) and the row stores, where an 80-byte padded
+// row spent half of its LDS cycles in bank conflicts (rocprofv3 on MI355X).
+constexpr int LROW = KS;
+__device__ inline int swz4(int row, int piece) { return (piece ^ ((row >> 1) & 3)) * 8; }
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -111,7 +116,13 @@ __global__ void c_transpose(const double* __restrict__ C, int64_t nao, int64_t n
 // chunk's 16-byte pieces are loaded into registers while the current chunk is
 // multiplied from the other LDS buffer.
 constexpr int KC16 = 64;
-constexpr int LROW64 = KC16 + 8;  // 72 halves = 144 bytes per LDS row
+// LDS rows of one 64-deep chunk: 8 pieces of 16 bytes, piece p of row r kept
+// at position p ^ (r & 7).  Measured on MI355X with rocprofv3
+// (SQ_LDS_BANK_CONFLICT): the operand reads (16 consecutive rows, one piece)
+// are conflict-free this way, while a padded 144-byte row spent half of its
+// LDS cycles in bank conflicts.
+constexpr int LROW64 = KC16;
+__device__ inline int swz(int row, int piece) { return (piece ^ (row & 7)) * 8; }
 
 template <typename H, int NI>
 struct G16Stage {
@@ -150,12 +161,12 @@ __device__ inline void g16_store(const G16Stage<H, NI>& st, H (*sA)[LROW64], H (
 #pragma unroll
     for (int j = 0; j < (NA + kT - 1) / kT; ++j) {
         const int e = tid + j * kT;
-        if (e < NA) *reinterpret_cast<u4*>(&sA[e >> 3][8 * (e & 7)]) = st.a[j];
+        if (e < NA) *reinterpret_cast<u4*>(&sA[e >> 3][swz(e >> 3, e & 7)]) = st.a[j];
     }
 #pragma unroll
     for (int j = 0; j < (NB + kT - 1) / kT; ++j) {
         const int e = tid + j * kT;
-        if (e < NB) *reinterpret_cast<u4*>(&sB[e >> 3][8 * (e & 7)]) = st.b[j];
+        if (e < NB) *reinterpret_cast<u4*>(&sB[e >> 3][swz(e >> 3, e & 7)]) = st.b[j];
     }
 }
 
@@ -194,13 +205,16 @@ __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ld
 #pragma unroll
         for (int ks = 0; ks < KC16 / KS; ++ks) {
             u4 a[2];
+            const int pc = ks * (KS / 8) + (lane >> 4);  // 16-byte piece of the chunk
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-                a[t] = *reinterpret_cast<const u4*>(
-                    &sA[buf][wave * 32 + t * 16 + (lane & 15)][ks * KS + 8 * (lane >> 4)]);
+            for (int t = 0; t < 2; ++t) {
+                const int r = wave * 32 + t * 16 + (lane & 15);
+                a[t] = *reinterpret_cast<const u4*>(&sA[buf][r][swz(r, pc)]);
+            }
 #pragma unroll
             for (int n = 0; n < NI; ++n) {
-                const u4 b = *reinterpret_cast<const u4*>(&sB[buf][n * 16 + (lane & 15)][ks * KS + 8 * (lane >> 4)]);
+                const int r = n * 16 + (lane & 15);
+                const u4 b = *reinterpret_cast<const u4*>(&sB[buf][r][swz(r, pc)]);
 #pragma unroll
                 for (int t = 0; t < 2; ++t) acc[t][n] = Mma16<H>::step(a[t], b, acc[t][n]);
             }
@@ -215,6 +229,119 @@ __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ld
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t mu = mu0 + wave * 32 + t * 16 + 4 * (lane >> 4) + r;
+                const int64_t i = i0 + n * 16 + (lane & 15);
+                if (mu < nao && i < ncp)
+                    X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[t][n][r] : 0.f);
+            }
+}
+
+// GEMM1, direct form: no two wavefronts share rows mu, so each wavefront
+// loads its A fragments (16-byte runs of dense B_P rows) straight from memory
+// into the matrix-core layout; only C^T, which all four share, is staged in
+// LDS.  Wavefront tile: 16*TM rows x 16*NI columns; workgroup: 4 wavefronts
+// stacked along mu (64*TM rows).  The next 64-deep chunk of both operands is
+// loaded into registers while the current one is multiplied.
+template <int NI>
+struct G16BStage {
+    u4 b[(16 * NI * KC16 / 8 + kT - 1) / kT];
+};
+
+template <typename H, int NI>
+__device__ inline void g16d_load_b(G16BStage<NI>& st, const H* __restrict__ Ct, int64_t ldd, int64_t ncp,
+                                   int64_t i0, int64_t k0, int tid) {
+    constexpr int NB = 16 * NI * KC16 / 8;
+#pragma unroll
+    for (int j = 0; j < (NB + kT - 1) / kT; ++j) {
+        const int e = tid + j * kT;
+        const int r = e >> 3, q = e & 7;
+        const int64_t i = i0 + r;
+        st.b[j] = (e < NB && i < ncp && k0 + 8 * q < ldd)
+                      ? *reinterpret_cast<const u4*>(Ct + i * ldd + k0 + 8 * q)
+                      : u4{0u, 0u, 0u, 0u};
+    }
+}
+
+template <typename H, int NI>
+__device__ inline void g16d_store_b(const G16BStage<NI>& st, H (*sB)[LROW64], int tid) {
+    constexpr int NB = 16 * NI * KC16 / 8;
+#pragma unroll
+    for (int j = 0; j < (NB + kT - 1) / kT; ++j) {
+        const int e = tid + j * kT;
+        if (e < NB) *reinterpret_cast<u4*>(&sB[e >> 3][swz(e >> 3, e & 7)]) = st.b[j];
+    }
+}
+
+template <typename H, int TM>
+__device__ inline void g16d_load_a(u4 (&fa)[TM][KC16 / KS], const H* __restrict__ A, int64_t ldd,
+                                   int64_t row0, int64_t k0, int lane) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+        const int64_t row = row0 + t * 16 + (lane & 15);
+#pragma unroll
+        for (int ks = 0; ks < KC16 / KS; ++ks) {
+            const int64_t k = k0 + ks * KS + 8 * (lane >> 4);
+            fa[t][ks] = (row < ldd && k < ldd) ? *reinterpret_cast<const u4*>(A + row * ldd + k)
+                                               : u4{0u, 0u, 0u, 0u};
+        }
+    }
+}
+
+template <typename H, int TM, int NI>
+__global__ __launch_bounds__(kT) void g1_16d(const H* __restrict__ Bd, int64_t ldd, int64_t nao,
+                                              const H* __restrict__ Ct, int64_t ncol, int64_t ncp,
+                                              H* __restrict__ X, int64_t nib, int64_t nmb, int64_t nblk) {
+    constexpr int BI = 16 * NI, BM = 64 * TM, NKS = KC16 / KS;
+    __shared__ H sB[2][BI][LROW64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t lid = xcd_lid(blockIdx.x, nblk);
+    const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
+    const int64_t i0 = ib * BI, row0 = mb * BM + wave * 16 * TM;
+    const H* A = Bd + P * ldd * ldd;
+    v4f acc[TM][NI];
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t nk = ldd / KC16 + (ldd % KC16 ? 1 : 0);
+    u4 fa[TM][NKS], fn[TM][NKS];
+    G16BStage<NI> st;
+    g16d_load_a<H, TM>(fa, A, ldd, row0, 0, lane);
+    g16d_load_b<H, NI>(st, Ct, ldd, ncp, i0, 0, tid);
+    g16d_store_b<H, NI>(st, sB[0], tid);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nk;
+        if (more) {
+            g16d_load_a<H, TM>(fn, A, ldd, row0, (kc + 1) * KC16, lane);
+            g16d_load_b<H, NI>(st, Ct, ldd, ncp, i0, (kc + 1) * KC16, tid);
+        }
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+            for (int n = 0; n < NI; ++n) {
+                const int r = n * 16 + (lane & 15);
+                const u4 b = *reinterpret_cast<const u4*>(&sB[buf][r][swz(r, ks * (KS / 8) + (lane >> 4))]);
+#pragma unroll
+                for (int t = 0; t < TM; ++t) acc[t][n] = Mma16<H>::step(fa[t][ks], b, acc[t][n]);
+            }
+        }
+        if (more) {
+            g16d_store_b<H, NI>(st, sB[buf ^ 1], tid);
+#pragma unroll
+            for (int t = 0; t < TM; ++t)
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) fa[t][ks] = fn[t][ks];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int n = 0; n < NI; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t mu = row0 + t * 16 + 4 * (lane >> 4) + r;
                 const int64_t i = i0 + n * 16 + (lane & 15);
                 if (mu < nao && i < ncp)
                     X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[t][n][r] : 0.f);
@@ -249,8 +376,8 @@ __device__ inline void s16_store(const S16Stage& st, H (*sA)[LROW], H (*sB)[LROW
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int e = tid + j * kT;
-        *reinterpret_cast<u4*>(&sA[e >> 2][8 * (e & 3)]) = st.a[j];
-        *reinterpret_cast<u4*>(&sB[e >> 2][8 * (e & 3)]) = st.b[j];
+        *reinterpret_cast<u4*>(&sA[e >> 2][swz4(e >> 2, e & 3)]) = st.a[j];
+        *reinterpret_cast<u4*>(&sB[e >> 2][swz4(e >> 2, e & 3)]) = st.b[j];
     }
 }
 
@@ -292,8 +419,9 @@ __global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t n
             u4 a[4], b[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                a[q] = *reinterpret_cast<const u4*>(&sA[buf][wm * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
-                b[q] = *reinterpret_cast<const u4*>(&sB[buf][wn * 64 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+                const int ra = wm * 64 + q * 16 + (lane & 15), rb = wn * 64 + q * 16 + (lane & 15);
+                a[q] = *reinterpret_cast<const u4*>(&sA[buf][ra][swz4(ra, lane >> 4)]);
+                b[q] = *reinterpret_cast<const u4*>(&sB[buf][rb][swz4(rb, lane >> 4)]);
             }
 #pragma unroll
             for (int ti = 0; ti < 4; ++ti)
@@ -347,10 +475,63 @@ __global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ pa
 template <typename H, int NI>
 void launch_g1(hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
                int64_t ncp, H* X, int64_t naux) {
-
     const int64_t nib = cdiv(ncp, 16 * NI), nmb = cdiv(nao, 128);
     const int64_t nblk = nib * nmb * naux;
     g1_16<H, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
+}
+
+template <typename H, int TM, int NI>
+void launch_g1d(hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
+                int64_t ncp, H* X, int64_t naux) {
+    const int64_t nib = cdiv(ncp, 16 * NI), nmb = cdiv(nao, 64 * TM);
+    const int64_t nblk = nib * nmb * naux;
+    g1_16d<H, TM, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
+}
+
+// Compiled 16-bit GEMM1 tiles: (orbital columns, basis-function rows) per
+// workgroup; the first three stage both operands in LDS, the rest load A
+// straight into registers.
+template <typename H>
+using G16Launch = void (*)(hipStream_t, const H*, int64_t, int64_t, const H*, int64_t, int64_t, H*, int64_t);
+struct G16Tile {
+    int cols, rows;
+};
+constexpr G16Tile kG16Tiles[] = {{64, 128}, {128, 128}, {208, 128}, {128, 128}, {208, 128},
+                                 {128, 256}, {64, 256}};
+constexpr int kNumG16Tiles = sizeof(kG16Tiles) / sizeof(kG16Tiles[0]);
+
+// Default tile: least padded orbital columns per unit of measured rate.  On
+// MI355X at nao=2048, naux=1024, nocc=400 (BF16) the tiles of 64, 128 and 208
+// columns (indices 0, 1, 4) executed 468, 740 and 741 TFLOP/s counting the
+// padded columns (435, 578 and 713 of useful work).
+inline int pick_g16_tile(int64_t ncp) {
+    static const int cand[3] = {0, 1, 4};
+    static const double rate[3] = {468.0, 740.0, 741.0};
+    int best = 1;
+    double best_cost = 1e300;
+    for (int c = 0; c < 3; ++c) {
+        const int64_t w = kG16Tiles[cand[c]].cols;
+        const double cost = (double)(cdiv(ncp, w) * w) / rate[c];
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = cand[c];
+        }
+    }
+    return best;
+}
+
+template <typename H>
+void launch_g16(int t, hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
+                int64_t ncp, H* X, int64_t naux) {
+    switch (t) {
+        case 0: launch_g1<H, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        case 1: launch_g1<H, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        case 2: launch_g1<H, 13>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        case 3: launch_g1d<H, 2, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        case 4: launch_g1d<H, 2, 13>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        case 5: launch_g1d<H, 4, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        default: launch_g1d<H, 4, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+    }
 }
 
 template <typename H>
@@ -377,18 +558,9 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     c_transpose<H><<<dim3((unsigned)cdiv(ncp * ldd, 256)), 256, 0, st>>>(C, nao, ncol, ncp, ldd, Ct);
     DFJK_LAUNCH_CHECK("c_transpose");
     h->prof.begin(PH_K_GEMM1, st);
-    // column tile: 64, 128 or 208 occupied orbitals (the handle's choice, else
-    // 128 unless nocc fits in 64: on MI355X at nao=2048, nocc=400 BF16 the
-    // 128-wide tile ran at 585 TFLOP/s against 444 for 208 (one wave per SIMD)
-    // and 440 for 64, although it pads 400 to 512)
     int t = h->k16_tile;
-    if (t < 0) t = ncp <= 64 ? 0 : 1;
-    if (t == 2)
-        launch_g1<H, 13>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
-    else if (t == 1)
-        launch_g1<H, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
-    else
-        launch_g1<H, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    if (t < 0 || t >= kNumG16Tiles) t = pick_g16_tile(ncp);
+    launch_g16<H>(t, st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
     const int64_t nt = cdiv(nao, 128), ntl = nt * (nt + 1) / 2;
@@ -421,6 +593,15 @@ int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double*
     if (h->dtype == DFJK_F16) return k16_t<_Float16>(h, C, ncol, scale, K);
     set_error("16-bit exchange needs BF16 or FP16 B");
     return DFJK_E_DTYPE;
+}
+
+int k16_tile_count() { return kNumG16Tiles; }
+
+int k16_tile_info(int index, int* cols, int* rows) {
+    if (index < 0 || index >= kNumG16Tiles) return DFJK_E_INVALID;
+    *cols = kG16Tiles[index].cols;
+    *rows = kG16Tiles[index].rows;
+    return DFJK_OK;
 }
 
 }  // namespace dfjk

@@ -143,9 +143,28 @@ __device__ inline void g1_addr_next(G1Addr<NI, WM>& ad, int64_t nu0, int64_t ldc
     }
 }
 
-template <typename T, int NI, int WM>
-__device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[16 * NI + 1],
-                                T (*sB)[64 * WM + 1], bool lower, int tid) {
+// LDS row pitches of the GEMM1 tiles.  An FP32 operand read covers 4 rows x
+// 16 consecutive columns (64 lanes, 64 banks): a pitch of 16 or 48 modulo 64
+// words puts the four rows on disjoint banks.  The B tile is also written
+// transposed (16 rows x 4 columns per wavefront), so its columns are XOR-ed
+// with g1_swz(row) < 16, which keeps every 16-column group in place for the
+// reads and spreads the transposed writes over all banks.  FP64 reads go 16
+// lanes at a time, so the FP64 tiles keep a pitch of one extra element.  With
+// B stored in 16 bits the compiler doubled the registers of the bank-free
+// layout (occupancy 4 -> 2 waves per SIMD, 20% slower on MI355X), so those
+// tiles keep the padded layout as well.
+template <typename T, typename TS>
+constexpr bool g1_bankfree() { return sizeof(T) == 4 && sizeof(TS) == 4; }
+template <typename T, typename TS, int BI>
+constexpr int g1_pitch_c() { return g1_bankfree<T, TS>() ? (BI % 32 == 16 ? BI : BI + 16) : BI + 1; }
+template <typename T, typename TS, int BM>
+constexpr int g1_pitch_b() { return g1_bankfree<T, TS>() ? BM + 16 : BM + 1; }
+template <typename T, typename TS>
+__device__ inline int g1_swz(int row) { return g1_bankfree<T, TS>() ? 2 * ((row >> 1) & 7) : 0; }
+
+template <typename T, typename TS, int NI, int WM>
+__device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[g1_pitch_c<T, TS, 16 * NI>()],
+                                T (*sB)[g1_pitch_b<T, TS, 64 * WM>()], bool lower, int tid) {
     constexpr int BI = 16 * NI, BM = 64 * WM, ROWS = kThreads / BM;
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
@@ -153,11 +172,15 @@ __device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[16 * NI + 
         sC[e / BI][e % BI] = st.c[j];
     }
     if (lower) {
+        const int r = tid % KC;
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) sB[tid % KC][tid / KC + 16 * j] = st.b[j];
+        for (int j = 0; j < 4 * WM; ++j) sB[r][(tid / KC + 16 * j) ^ g1_swz<T, TS>(r)] = st.b[j];
     } else {
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) sB[tid / BM + ROWS * j][tid % BM] = st.b[j];
+        for (int j = 0; j < 4 * WM; ++j) {
+            const int r = tid / BM + ROWS * j;
+            sB[r][(tid % BM) ^ g1_swz<T, TS>(r)] = st.b[j];
+        }
     }
 }
 
@@ -180,8 +203,8 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                     T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb) {
     constexpr int BI = 16 * NI, BM = 64 * WM;
-    __shared__ T sC[2][KC][BI + 1];
-    __shared__ T sB[2][KC][BM + 1];
+    __shared__ T sC[2][KC][g1_pitch_c<T, TS, BI>()];
+    __shared__ T sB[2][KC][g1_pitch_b<T, TS, BM>()];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, mu0 = mb * BM;
@@ -198,7 +221,7 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
     G1Addr<NI, WM> ad;
     g1_addr_init<NI, WM>(ad, nao, ldc, ncol, mu0, i0, tid);
     g1_load<T, TS, NI, WM>(st, ad, Bp, nao, C, 0, mu0, tid);
-    g1_store<T, NI, WM>(st, sC[0], sB[0], KC <= mu0, tid);
+    g1_store<T, TS, NI, WM>(st, sC[0], sB[0], KC <= mu0, tid);
     __syncthreads();
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
@@ -215,13 +238,13 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
 #pragma unroll
             for (int t = 0; t < NI; ++t) a[t] = sC[buf][kr][t * 16 + (lane & 15)];
 #pragma unroll
-            for (int t = 0; t < WM; ++t) b[t] = sB[buf][kr][wave * 16 * WM + t * 16 + (lane & 15)];
+            for (int t = 0; t < WM; ++t) b[t] = sB[buf][kr][(wave * 16 * WM + t * 16 + (lane & 15)) ^ g1_swz<T, TS>(kr)];
 #pragma unroll
             for (int ti = 0; ti < NI; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < WM; ++tj) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
         }
-        if (more) g1_store<T, NI, WM>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
+        if (more) g1_store<T, TS, NI, WM>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
         __syncthreads();
     }
 #pragma unroll
@@ -274,8 +297,10 @@ template <typename T>
 __device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                    int64_t nao, int64_t ncol, const double* __restrict__ sign,
                                    int64_t kchunk, int64_t ntl, T* __restrict__ part) {
-    __shared__ T sA[2][KC][SY_T + 1];
-    __shared__ T sB[2][KC][SY_T + 1];
+    // FP32 reads cover 4 rows x 16 columns over 64 banks: pitch 144 = 16 mod 64
+    constexpr int PS = sizeof(T) == 4 ? SY_T + 16 : SY_T + 1;
+    __shared__ T sA[2][KC][PS];
+    __shared__ T sB[2][KC][PS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t t = lid % ntl;
