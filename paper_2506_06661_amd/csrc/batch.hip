@@ -22,6 +22,8 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kBuckets = 8;
+constexpr int64_t kBatchJRows = 256;      // most B rows one J pass-2 workgroup walks
+constexpr int64_t kBatchSyrkRows = 4096;  // most (P, i) rows one SYRK workgroup sums
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -238,12 +240,23 @@ int dfjk_batch_init(dfjk_batch* out, const dfjk_mol* mols, int nmol, int dtype, 
         d.j_chunks = std::min(std::max<int64_t>(chunks, 1), max_chunks);
         d.chunk = cdiv(cdiv(d.npair, d.j_chunks), V) * V;
         const int64_t colblocks = cdiv(d.npair, kT * V);
-        d.j_splits = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(cdiv(64, colblocks), 1), 64), d.naux);
+        // pass 2: at least 64 workgroups per molecule, and none walking more
+        // than kBatchJRows rows of B (long serial walks left the pass at
+        // 3.8 TB/s on MI355X)
+        d.j_splits = std::min<int64_t>(
+            std::min<int64_t>(std::max<int64_t>(std::max<int64_t>(cdiv(64, colblocks), cdiv(d.naux, kBatchJRows)), 1),
+                              64),
+            d.naux);
         d.prows = cdiv(d.naux, d.j_splits);
         const int64_t nt = cdiv(d.nao, 128);
         d.ntl = nt * (nt + 1) / 2;
         const int64_t nrows = d.naux * d.nocc;
-        int64_t nsplit = std::min<int64_t>(std::max<int64_t>(cdiv(32, d.ntl), 1), cdiv(nrows, 256));
+        // SYRK: at least 32 workgroups per molecule, and none longer than
+        // kBatchSyrkRows rows of the (P, i) contraction: bounds the FP32 running
+        // sums and the launch's tail (with 4 splits per molecule the largest
+        // molecules' blocks ran alone at the end: 56 ms of a 130 ms build)
+        int64_t nsplit = std::min<int64_t>(std::max<int64_t>(std::max<int64_t>(cdiv(32, d.ntl), cdiv(nrows, kBatchSyrkRows)), 1),
+                                           cdiv(nrows, 256));
         nsplit = std::max<int64_t>(nsplit, 1);
         d.kchunk = cdiv(cdiv(nrows, nsplit), 16) * 16;
         d.nsplit = cdiv(nrows, d.kchunk);
