@@ -108,9 +108,11 @@ def test_every_gemm1_tile(pkg):
         assert max_rel(K, K_ref) < TOL, (t, pkg.dfjk_tile_info(pkg.DFJK_TILE_GEMM1, t))
 
 
-def test_every_j_out_width(pkg):
-    """Each compiled J pass-2 column width gives the oracle's J."""
-    nao, naux, nocc = 300, 33, 5
+@pytest.mark.parametrize("naux", [33, 1000])
+def test_every_j_out_width(pkg, naux):
+    """Each compiled J pass-2 variant gives the oracle's J (naux=1000 makes
+    the row slices long enough for the multi-row loads and their tails)."""
+    nao, nocc = 300, 5
     R, B, C = system(nao, naux, nocc, 26)
     D = 2 * C @ C.T
     J_ref = oracle.J(B, nao, D)
