@@ -149,22 +149,25 @@ __device__ inline void g1_addr_next(G1Addr<NI, WM>& ad, int64_t nu0, int64_t ldc
 // transposed (16 rows x 4 columns per wavefront), so its columns are XOR-ed
 // with g1_swz(row) < 16, which keeps every 16-column group in place for the
 // reads and spreads the transposed writes over all banks.  FP64 reads go 16
-// lanes at a time, so the FP64 tiles keep a pitch of one extra element.  With
-// B stored in 16 bits the compiler doubled the registers of the bank-free
-// layout (occupancy 4 -> 2 waves per SIMD, 20% slower on MI355X), so those
-// tiles keep the padded layout as well.
-template <typename T, typename TS>
-constexpr bool g1_bankfree() { return sizeof(T) == 4 && sizeof(TS) == 4; }
-template <typename T, typename TS, int BI>
-constexpr int g1_pitch_c() { return g1_bankfree<T, TS>() ? (BI % 32 == 16 ? BI : BI + 16) : BI + 1; }
-template <typename T, typename TS, int BM>
-constexpr int g1_pitch_b() { return g1_bankfree<T, TS>() ? BM + 16 : BM + 1; }
-template <typename T, typename TS>
-__device__ inline int g1_swz(int row) { return g1_bankfree<T, TS>() ? 2 * ((row >> 1) & 7) : 0; }
+// lanes at a time, so the FP64 tiles keep a pitch of one extra element.  The
+// per-row XOR costs address registers: on MI355X the bank-free layout was
+// faster only for FP32 storage and the (5, 1) tile (the FP32 default: 26.0 ->
+// 25.0 ms at nao=1024, naux=4096, nocc=200); wider tiles and 16-bit storage
+// lost occupancy and ran up to 1.6x slower, so they keep the padded layout.
+template <typename T, typename TS, int NI, int WM>
+constexpr bool g1_bankfree() { return sizeof(T) == 4 && sizeof(TS) == 4 && WM == 1 && NI <= 5; }
+template <typename T, typename TS, int NI, int WM>
+constexpr int g1_pitch_c() {
+    return g1_bankfree<T, TS, NI, WM>() ? ((16 * NI) % 32 == 16 ? 16 * NI : 16 * NI + 16) : 16 * NI + 1;
+}
+template <typename T, typename TS, int NI, int WM>
+constexpr int g1_pitch_b() { return g1_bankfree<T, TS, NI, WM>() ? 64 * WM + 16 : 64 * WM + 1; }
+template <typename T, typename TS, int NI, int WM>
+__device__ inline int g1_swz(int row) { return g1_bankfree<T, TS, NI, WM>() ? 2 * ((row >> 1) & 7) : 0; }
 
 template <typename T, typename TS, int NI, int WM>
-__device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[g1_pitch_c<T, TS, 16 * NI>()],
-                                T (*sB)[g1_pitch_b<T, TS, 64 * WM>()], bool lower, int tid) {
+__device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[g1_pitch_c<T, TS, NI, WM>()],
+                                T (*sB)[g1_pitch_b<T, TS, NI, WM>()], bool lower, int tid) {
     constexpr int BI = 16 * NI, BM = 64 * WM, ROWS = kThreads / BM;
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
@@ -174,12 +177,12 @@ __device__ inline void g1_store(const G1Stage<T, NI, WM>& st, T (*sC)[g1_pitch_c
     if (lower) {
         const int r = tid % KC;
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) sB[r][(tid / KC + 16 * j) ^ g1_swz<T, TS>(r)] = st.b[j];
+        for (int j = 0; j < 4 * WM; ++j) sB[r][(tid / KC + 16 * j) ^ g1_swz<T, TS, NI, WM>(r)] = st.b[j];
     } else {
 #pragma unroll
         for (int j = 0; j < 4 * WM; ++j) {
             const int r = tid / BM + ROWS * j;
-            sB[r][(tid % BM) ^ g1_swz<T, TS>(r)] = st.b[j];
+            sB[r][(tid % BM) ^ g1_swz<T, TS, NI, WM>(r)] = st.b[j];
         }
     }
 }
@@ -203,8 +206,8 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                     T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb) {
     constexpr int BI = 16 * NI, BM = 64 * WM;
-    __shared__ T sC[2][KC][g1_pitch_c<T, TS, BI>()];
-    __shared__ T sB[2][KC][g1_pitch_b<T, TS, BM>()];
+    __shared__ T sC[2][KC][g1_pitch_c<T, TS, NI, WM>()];
+    __shared__ T sB[2][KC][g1_pitch_b<T, TS, NI, WM>()];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, mu0 = mb * BM;
@@ -238,7 +241,7 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
 #pragma unroll
             for (int t = 0; t < NI; ++t) a[t] = sC[buf][kr][t * 16 + (lane & 15)];
 #pragma unroll
-            for (int t = 0; t < WM; ++t) b[t] = sB[buf][kr][(wave * 16 * WM + t * 16 + (lane & 15)) ^ g1_swz<T, TS>(kr)];
+            for (int t = 0; t < WM; ++t) b[t] = sB[buf][kr][(wave * 16 * WM + t * 16 + (lane & 15)) ^ g1_swz<T, TS, NI, WM>(kr)];
 #pragma unroll
             for (int ti = 0; ti < NI; ++ti)
 #pragma unroll
