@@ -7,6 +7,7 @@ the only thing both sides use is the input generator in ``synth``.
 
 Contents, each following the passage it cites:
 
+* ``df_diagonal`` -- sum_P T[P, mu nu]^2 per packed pair (Sec. IV.C.2).
 * ``rho``, ``J``, ``K_C``, ``K_D``, ``K_C_rows`` -- the J/K contractions of
   Sec. IV.C.2, Eq. eq:df:eri, written as plain loops in ``oracle.c``.
 * ``energies`` -- E_J = 1/2 sum_P rho_P^2 = 1/2 tr(DJ) and E_K = -1/4 tr(DK).
@@ -144,6 +145,18 @@ def K_C_rows(Bsel: np.ndarray, C: np.ndarray) -> np.ndarray:
     out = np.zeros((nsel, nsel))
     if lib().oracle_K_C_rows(_dp(Bsel), nsel, nao, naux, _dp(C), C.shape[1], _dp(out)) != 0:
         raise MemoryError("oracle_K_C_rows")
+    return out
+
+
+def df_diagonal(B: np.ndarray, nao: int) -> np.ndarray:
+    """DF approximation of the diagonal integrals (mu nu|mu nu) = sum_P
+    T[P, mu nu]^2, in packed pair order: the fitted half of the diagonal error
+    measure of Sec. IV.C.2 (the exact half needs an integral engine)."""
+    npair = nao * (nao + 1) // 2
+    Bp = _f64(B)[:, :npair]
+    out = np.zeros(npair)
+    for P in range(Bp.shape[0]):  # plain sum over the auxiliary index
+        out += Bp[P] * Bp[P]
     return out
 
 

@@ -76,6 +76,28 @@ def test_bruteforce_four_index(c1):
     assert rel(oracle.J(B, nao, A), np.einsum("mnkl,kl->mn", eri, A)) < 1e-13
 
 
+def test_df_diagonal_bruteforce(c1):
+    """The DF diagonal is the diagonal (mu nu|mu nu) of the brute-force
+    four-index tensor of Eq. eq:df:eri, in tril order; it is non-negative,
+    bounds every integral by Cauchy-Schwarz, and scales as s^2 with B."""
+    cfg, B, _, _ = c1
+    nao = cfg.nao
+    Bf = unpack_np(B, nao)
+    Bm = Bf.reshape(cfg.naux, nao * nao)
+    eri = (Bm.T @ Bm).reshape(nao, nao, nao, nao)
+    r, c = np.tril_indices(nao)
+    ref = eri[r, c, r, c]
+    d = oracle.df_diagonal(B, nao)
+    assert rel(d, ref) < 1e-14
+    assert np.all(d >= 0)
+    pair = eri[r, c][:, r, c]  # (p|q) over packed pairs
+    assert np.all(pair ** 2 <= np.outer(d, d) * (1 + 1e-12) + 1e-300)
+    assert rel(oracle.df_diagonal(3.0 * B, nao), 9.0 * d) < 1e-15
+    # padding beyond npair is ignored
+    Bpad = np.concatenate([B, np.full((B.shape[0], 5), 7.0)], axis=1)
+    assert np.array_equal(oracle.df_diagonal(Bpad, nao), d)
+
+
 def test_closed_form_rank_one():
     """naux = 1, B_1 = u u^T: J = K = (u^T D u) u u^T."""
     rng = np.random.default_rng(1)
