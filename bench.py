@@ -569,6 +569,19 @@ def main():
                       "traffic": traffic.get("j_out_" + args.dtype)},
         },
     }
+    # J with the DF diagonal from the same stream (sum_P B[P,p]^2)
+    dg = torch.empty(cfg.npair, dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J_diag(h.h, Dd, J, None, dg)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        pkg.dfjk_build_J_diag(h.h, Dd, J, None, dg)
+    e1.record()
+    torch.cuda.synchronize()
+    jd_ms = e0.elapsed_time(e1) / args.steps
+    res["j_with_df_diagonal"] = {"ms": jd_ms, "hbm_gbs": jbytes / jd_ms / 1e6,
+                                 "overhead_vs_j": jd_ms / j_ms - 1.0}
+    del dg
     res["measured_mfma_ceiling_tflops"] = {
         "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
         "bf16_16x16x32": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}

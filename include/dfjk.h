@@ -108,6 +108,19 @@ int dfjk_init(dfjk_handle* h, const void* B_dev, int dtype, int64_t nao, int64_t
 int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev);
 
 /*
+ * dfjk_build_J plus the DF diagonal from the same pass over B:
+ *   diag_dev[p(mu,nu)] = sum_P B[P, p(mu,nu)]^2,  p = max(mu,nu)(max+1)/2 + min,
+ * the density-fitted (mu nu|mu nu), whose difference from the exact diagonal
+ * integrals is the fitting error measure of Sec. IV.C.2.  diag_dev: device,
+ * npair = nao(nao+1)/2 FP64 values, caller-owned.  Products and sums in FP64
+ * of the stored B values (exact squares for FP32/BF16/FP16 B); deterministic.
+ * J and rho are bitwise those of dfjk_build_J.  The handle allocates
+ * j-splits x npair FP64 of workspace on the first call.
+ * Errors: as dfjk_build_J; DFJK_E_INVALID if diag_dev is NULL.
+ */
+int dfjk_build_J_diag(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev, double* diag_dev);
+
+/*
  * Exchange matrix, written in full (both triangles):
  *   Cocc_dev != NULL: K = 2 sum_P (B_P C)(B_P C)^T with C = Cocc_dev
  *                     (nao x nocc, 1 <= nocc <= nao), i.e. K for D = 2 C C^T.

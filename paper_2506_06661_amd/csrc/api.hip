@@ -139,7 +139,17 @@ int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_
         set_error("dfjk_build_J: null D or J");
         return DFJK_E_INVALID;
     }
-    return j_build(h, D_dev, J_dev, rho_dev);
+    return j_build(h, D_dev, J_dev, rho_dev, nullptr);
+}
+
+int dfjk_build_J_diag(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev, double* diag_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!D_dev || !J_dev || !diag_dev) {
+        set_error("dfjk_build_J_diag: null D, J or diag");
+        return DFJK_E_INVALID;
+    }
+    return j_build(h, D_dev, J_dev, rho_dev, diag_dev);
 }
 
 int dfjk_build_K_factored(dfjk_handle h, const double* C_dev, int64_t ncol, const double* sign_dev,
@@ -283,7 +293,7 @@ int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes) {
         set_error("dfjk_workspace_bytes: null output");
         return DFJK_E_INVALID;
     }
-    *bytes = h->dt.bytes + h->rho_part.bytes + h->rho.bytes + h->jpart.bytes + h->X.bytes +
+    *bytes = h->dt.bytes + h->rho_part.bytes + h->rho.bytes + h->jpart.bytes + h->dpart.bytes + h->X.bytes +
              h->kpart.bytes + h->ones.bytes + h->Cw.bytes + h->eig.bytes + h->Bdense.bytes;
     return DFJK_OK;
 }
@@ -365,6 +375,7 @@ void dfjk_destroy(dfjk_handle h) {
     h->rho_part.release();
     h->rho.release();
     h->jpart.release();
+    h->dpart.release();
     h->X.release();
     h->kpart.release();
     h->ones.release();

@@ -74,6 +74,7 @@ struct dfjk_ctx {
     dfjk::DevBuf rho_part;  // naux x j_chunks partial sums
     dfjk::DevBuf rho;       // naux
     dfjk::DevBuf jpart;     // j_splits x npair partial sums
+    dfjk::DevBuf dpart;     // j_splits x npair partial sums of B^2 (DF diagonal, on request)
     int j_chunks = 1, j_splits = 1;
 
     // K workspace
@@ -101,7 +102,7 @@ namespace dfjk {
 
 // J launchers (j_kernels.hip)
 int j_setup(dfjk_ctx* h);
-int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out);
+int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* diag);
 int j_out_count();
 
 // K launchers (k_kernels.hip)

@@ -120,20 +120,21 @@ __global__ void j_rho_finish(const double* __restrict__ part, int64_t naux, int 
 }
 
 // U = double2 loads per row per thread: a workgroup owns 512*U packed columns
-// (a 4U-KB run of each row it visits).
-template <bool VEC, int U>
+// (a 4U-KB run of each row it visits).  With DG the same stream also sums
+// B[P,p]^2 (the DF diagonal) into dpart.
+template <bool VEC, int U, bool DG>
 __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__ B, int64_t ldB,
                                                        int64_t naux, int64_t npair,
                                                        const double* __restrict__ rho, int64_t prows,
-                                                       double* __restrict__ jpart) {
+                                                       double* __restrict__ jpart, double* __restrict__ dpart) {
     constexpr int64_t COLS = (int64_t)kThreads * 2 * U;
     const int s = blockIdx.y;
     const int64_t P0 = (int64_t)s * prows;
     const int64_t P1 = P0 + prows < naux ? P0 + prows : naux;
     const int64_t base = (int64_t)blockIdx.x * COLS;
-    double acc[2 * U];
+    double acc[2 * U], sq[2 * U];  // sq is dead code without DG
 #pragma unroll
-    for (int u = 0; u < 2 * U; ++u) acc[u] = 0.0;
+    for (int u = 0; u < 2 * U; ++u) acc[u] = sq[u] = 0.0;
     // columns of this thread: base + u*2*kThreads + 2*tid + {0,1}
     const int64_t col0 = base + 2 * (int64_t)threadIdx.x;
     const bool full = base + COLS <= npair;
@@ -147,6 +148,10 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
                 const d2 b = __builtin_nontemporal_load(reinterpret_cast<const d2*>(row + u * 2 * kThreads));
                 acc[2 * u] = fma(b.x, r, acc[2 * u]);
                 acc[2 * u + 1] = fma(b.y, r, acc[2 * u + 1]);
+                if (DG) {
+                    sq[2 * u] = fma(b.x, b.x, sq[2 * u]);
+                    sq[2 * u + 1] = fma(b.y, b.y, sq[2 * u + 1]);
+                }
             }
         }
     } else {
@@ -158,7 +163,11 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int64_t col = col0 + u * 2 * kThreads + e;
-                    if (col < npair) acc[2 * u + e] = fma(row[col], r, acc[2 * u + e]);
+                    if (col < npair) {
+                        const double b = row[col];
+                        acc[2 * u + e] = fma(b, r, acc[2 * u + e]);
+                        if (DG) sq[2 * u + e] = fma(b, b, sq[2 * u + e]);
+                    }
                 }
             }
         }
@@ -169,18 +178,38 @@ __global__ __launch_bounds__(kThreads) void j_out_f64(const double* __restrict__
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int64_t col = col0 + u * 2 * kThreads + e;
-            if (col < npair) out[col] = acc[2 * u + e];
+            if (col < npair) {
+                out[col] = acc[2 * u + e];
+                if (DG) dpart[(int64_t)s * npair + col] = sq[2 * u + e];
+            }
         }
     }
 }
 
 template <int U>
 void launch_j_out(bool vec, dim3 g, hipStream_t st, const double* B, int64_t ldB, int64_t naux,
-                  int64_t npair, const double* rho, int64_t prows, double* jpart) {
-    if (vec)
-        j_out_f64<true, U><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart);
-    else
-        j_out_f64<false, U><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart);
+                  int64_t npair, const double* rho, int64_t prows, double* jpart, double* dpart) {
+    if (dpart) {
+        if (vec)
+            j_out_f64<true, U, true><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart, dpart);
+        else
+            j_out_f64<false, U, true><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart, dpart);
+    } else {
+        if (vec)
+            j_out_f64<true, U, false><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart, nullptr);
+        else
+            j_out_f64<false, U, false><<<g, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, jpart, nullptr);
+    }
+}
+
+// diag[p] = sum_s dpart[s][p], splits in order
+__global__ __launch_bounds__(256) void diag_finish(const double* __restrict__ dpart, int64_t npair, int nsplit,
+                                                   double* __restrict__ diag) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= npair) return;
+    double v = 0.0;
+    for (int s = 0; s < nsplit; ++s) v += dpart[(int64_t)s * npair + p];
+    diag[p] = v;
 }
 
 constexpr int kJOutU[] = {2, 4, 8, 16};
@@ -339,16 +368,22 @@ __global__ __launch_bounds__(kThreads) void j_rho_red(const TB* __restrict__ B, 
                                vec, part);
 }
 
-template <typename TB, int ACC>
+// With DG the stream also sums B[P,p]^2 in FP64 (exact products of the
+// stored values) into dpart: the DF diagonal.
+template <typename TB, int ACC, bool DG = false>
 __device__ inline void j_out_red_body(int64_t bx, int s, const TB* __restrict__ B, int64_t ldB,
                                       int64_t naux, int64_t npair, const double* __restrict__ rho,
                                       const float* __restrict__ rhi, const float* __restrict__ rlo,
-                                      int64_t prows, bool vec, double* __restrict__ jpart) {
+                                      int64_t prows, bool vec, double* __restrict__ jpart,
+                                      double* __restrict__ dpart = nullptr) {
     constexpr int V = Elem<TB>::V;
     const int64_t P0 = (int64_t)s * prows;
     const int64_t P1 = P0 + prows < naux ? P0 + prows : naux;
     const int64_t col0 = (bx * kThreads + threadIdx.x) * V;
     Acc<ACC> acc[V];
+    double sq[V];  // dead code without DG
+#pragma unroll
+    for (int v = 0; v < V; ++v) sq[v] = 0.0;
     if (vec && col0 + V <= npair) {
 #pragma unroll 4
         for (int64_t P = P0; P < P1; ++P) {
@@ -358,7 +393,10 @@ __device__ inline void j_out_red_body(int64_t bx, int s, const TB* __restrict__ 
             float b[V];
             load16<TB>(B + P * ldB + col0, b);
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v].add(b[v], m, mh, ml);
+            for (int v = 0; v < V; ++v) {
+                acc[v].add(b[v], m, mh, ml);
+                if (DG) sq[v] = fma((double)b[v], (double)b[v], sq[v]);
+            }
         }
     } else {
         for (int64_t P = P0; P < P1; ++P) {
@@ -367,26 +405,35 @@ __device__ inline void j_out_red_body(int64_t bx, int s, const TB* __restrict__ 
             const float ml = ACC == ACC_DOT2 ? rlo[P] : 0.f;
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if (col0 + v < npair) acc[v].add(Elem<TB>::f(B[P * ldB + col0 + v]), m, mh, ml);
+                if (col0 + v < npair) {
+                    const float bv = Elem<TB>::f(B[P * ldB + col0 + v]);
+                    acc[v].add(bv, m, mh, ml);
+                    if (DG) sq[v] = fma((double)bv, (double)bv, sq[v]);
+                }
         }
     }
     double* out = jpart + (int64_t)s * npair;
 #pragma unroll
     for (int v = 0; v < V; ++v)
-        if (col0 + v < npair) out[col0 + v] = acc[v].value();
+        if (col0 + v < npair) {
+            out[col0 + v] = acc[v].value();
+            if (DG) dpart[(int64_t)s * npair + col0 + v] = sq[v];
+        }
 }
 
-template <typename TB, int ACC>
+template <typename TB, int ACC, bool DG>
 __global__ __launch_bounds__(kThreads) void j_out_red(const TB* __restrict__ B, int64_t ldB, int64_t naux,
                                                        int64_t npair, const double* __restrict__ rho,
                                                        const float* __restrict__ rhi,
                                                        const float* __restrict__ rlo, int64_t prows,
-                                                       bool vec, double* __restrict__ jpart) {
-    j_out_red_body<TB, ACC>(blockIdx.x, blockIdx.y, B, ldB, naux, npair, rho, rhi, rlo, prows, vec, jpart);
+                                                       bool vec, double* __restrict__ jpart,
+                                                       double* __restrict__ dpart) {
+    j_out_red_body<TB, ACC, DG>(blockIdx.x, blockIdx.y, B, ldB, naux, npair, rho, rhi, rlo, prows, vec, jpart,
+                                dpart);
 }
 
 template <typename TB, int ACC>
-int j_build_red_t(dfjk_ctx* h, double* J, double* rho_out) {
+int j_build_red_t(dfjk_ctx* h, double* J, double* rho_out, double* diag) {
     constexpr int V = Elem<TB>::V;
     // rows per workgroup in pass 1: each FP64 (or FP32 hi/lo) weight is loaded
     // once per R rows, so 16-bit B uses more rows to keep that traffic small
@@ -423,23 +470,37 @@ int j_build_red_t(dfjk_ctx* h, double* J, double* rho_out) {
     }
     const int64_t prows = cdiv(h->naux, h->j_splits);
     const dim3 g2((unsigned)cdiv(h->npair, (int64_t)kThreads * V), (unsigned)h->j_splits);
+    double* dpart = nullptr;
+    if (diag) {
+        int rc;
+        if ((rc = h->dpart.ensure(sizeof(double) * (size_t)h->npair * (size_t)h->j_splits))) return rc;
+        dpart = static_cast<double*>(h->dpart.ptr);
+    }
     h->prof.begin(PH_J_OUT, st);
-    j_out_red<TB, ACC><<<g2, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, rho, rhi, rlo, prows, vec,
-                                                jpart);
+    if (dpart)
+        j_out_red<TB, ACC, true><<<g2, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, rho, rhi, rlo, prows,
+                                                          vec, jpart, dpart);
+    else
+        j_out_red<TB, ACC, false><<<g2, kThreads, 0, st>>>(B, h->ldB, h->naux, h->npair, rho, rhi, rlo, prows,
+                                                           vec, jpart, nullptr);
     h->prof.end(PH_J_OUT, st);
     DFJK_LAUNCH_CHECK("j_out_red");
     j_finish<<<dim3((unsigned)h->nao), kThreads, 0, st>>>(jpart, h->npair, h->j_splits, h->nao, J);
-    h->prof.end(PH_J, st);
     DFJK_LAUNCH_CHECK("j_finish");
+    if (dpart) {
+        diag_finish<<<dim3((unsigned)cdiv(h->npair, 256)), 256, 0, st>>>(dpart, h->npair, h->j_splits, diag);
+        DFJK_LAUNCH_CHECK("diag_finish");
+    }
+    h->prof.end(PH_J, st);
     return DFJK_OK;
 }
 
 template <typename TB>
-int j_build_red(dfjk_ctx* h, double* J, double* rho_out) {
+int j_build_red(dfjk_ctx* h, double* J, double* rho_out, double* diag) {
     switch (h->opts.compensated_j) {
-        case ACC_F32: return j_build_red_t<TB, ACC_F32>(h, J, rho_out);
-        case ACC_DOT2: return j_build_red_t<TB, ACC_DOT2>(h, J, rho_out);
-        default: return j_build_red_t<TB, ACC_F64>(h, J, rho_out);
+        case ACC_F32: return j_build_red_t<TB, ACC_F32>(h, J, rho_out, diag);
+        case ACC_DOT2: return j_build_red_t<TB, ACC_DOT2>(h, J, rho_out, diag);
+        default: return j_build_red_t<TB, ACC_F64>(h, J, rho_out, diag);
     }
 }
 
@@ -545,16 +606,16 @@ int j_setup(dfjk_ctx* h) {
     return DFJK_OK;
 }
 
-int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out) {
+int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* diag) {
     double* dt = static_cast<double*>(h->dt.ptr);
     const hipStream_t st = h->stream;
     h->prof.begin(PH_J, st);
     pack_density<<<dim3((unsigned)h->nao), dim3(kThreads), 0, st>>>(D, h->nao, dt);
     DFJK_LAUNCH_CHECK("pack_density");
     switch (h->dtype) {
-        case DFJK_F32: return j_build_red<float>(h, J, rho_out);
-        case DFJK_BF16: return j_build_red<uint16_t>(h, J, rho_out);
-        case DFJK_F16: return j_build_red<_Float16>(h, J, rho_out);
+        case DFJK_F32: return j_build_red<float>(h, J, rho_out, diag);
+        case DFJK_BF16: return j_build_red<uint16_t>(h, J, rho_out, diag);
+        case DFJK_F16: return j_build_red<_Float16>(h, J, rho_out, diag);
         default: break;
     }
     const double* B = static_cast<const double*>(h->B);
@@ -587,18 +648,28 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out) {
     j_out_geometry(h, U, &splits);
     const int64_t prows = cdiv(h->naux, splits);
     const dim3 g2((unsigned)cdiv(h->npair, (int64_t)kThreads * 2 * U), (unsigned)splits);
+    double* dpart = nullptr;
+    if (diag) {
+        int rc;
+        if ((rc = h->dpart.ensure(sizeof(double) * (size_t)h->npair * (size_t)splits))) return rc;
+        dpart = static_cast<double*>(h->dpart.ptr);
+    }
     h->prof.begin(PH_J_OUT, st);
     switch (U) {
-        case 2: launch_j_out<2>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
-        case 4: launch_j_out<4>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
-        case 8: launch_j_out<8>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
-        default: launch_j_out<16>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart); break;
+        case 2: launch_j_out<2>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart, dpart); break;
+        case 4: launch_j_out<4>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart, dpart); break;
+        case 8: launch_j_out<8>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart, dpart); break;
+        default: launch_j_out<16>(vec, g2, st, B, h->ldB, h->naux, h->npair, rho, prows, jpart, dpart); break;
     }
     h->prof.end(PH_J_OUT, st);
     DFJK_LAUNCH_CHECK("j_out_f64");
     j_finish<<<dim3((unsigned)h->nao), kThreads, 0, st>>>(jpart, h->npair, (int)splits, h->nao, J);
-    h->prof.end(PH_J, st);
     DFJK_LAUNCH_CHECK("j_finish");
+    if (dpart) {
+        diag_finish<<<dim3((unsigned)cdiv(h->npair, 256)), 256, 0, st>>>(dpart, h->npair, (int)splits, diag);
+        DFJK_LAUNCH_CHECK("diag_finish");
+    }
+    h->prof.end(PH_J, st);
     return DFJK_OK;
 }
 

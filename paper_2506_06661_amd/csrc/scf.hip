@@ -266,7 +266,7 @@ int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, i
     const unsigned g2 = (unsigned)cdiv(n2, 256);
 
     // J and K of the current density
-    if ((rc = j_build(h, D, ws.J, nullptr))) return rc;
+    if ((rc = j_build(h, D, ws.J, nullptr, nullptr))) return rc;
     if (flags & DFJK_SCF_C_VALID)
         rc = k_build_factored(h, C, nocc, nullptr, 2.0, ws.K);
     else

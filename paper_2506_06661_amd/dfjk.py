@@ -63,6 +63,7 @@ def lib():
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
         L.dfjk_init.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i64, i64, vp, ctypes.POINTER(Options)]
         L.dfjk_build_J.argtypes = [vp, vp, vp, vp]
+        L.dfjk_build_J_diag.argtypes = [vp, vp, vp, vp, vp]
         L.dfjk_build_K.argtypes = [vp, vp, i64, vp, vp]
         L.dfjk_build_K_factored.argtypes = [vp, vp, i64, vp, dbl, vp]
         L.dfjk_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -162,6 +163,10 @@ def dfjk_init(B, dtype: int, nao: int, naux: int, ldB: int, stream=None, opts: O
 
 def dfjk_build_J(h, D, J, rho=None) -> int:
     return _check("dfjk_build_J", lib().dfjk_build_J(h, _ptr(D), _ptr(J), _ptr(rho)))
+
+
+def dfjk_build_J_diag(h, D, J, rho, diag) -> int:
+    return _check("dfjk_build_J_diag", lib().dfjk_build_J_diag(h, _ptr(D), _ptr(J), _ptr(rho), _ptr(diag)))
 
 
 def dfjk_build_K(h, Cocc, nocc: int, D, K) -> int:

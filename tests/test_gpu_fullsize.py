@@ -124,8 +124,17 @@ def test_c2_fp64_full(pkg, c2):
     assert np.array_equal(K, K.T)
     ej, ej_o = 0.5 * float(rho @ rho), 0.5 * float(rho_o @ rho_o)
     assert abs(ej - ej_o) < 1e-10 * abs(ej_o)
+    # DF diagonal from the same J stream
+    h = pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao)
+    Jd = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+    dg = torch.empty(cfg.npair, dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J_diag(h.h, torch.from_numpy(D).cuda(), Jd, None, dg)
+    h.close()
+    d_o = oracle.df_diagonal(B, cfg.nao)
+    err_d = float(np.abs(host(dg) - d_o).max() / d_o.max())
+    assert err_d < 1e-12 and np.array_equal(host(Jd), J)
     print(f"C2 FP64: rho {max_rel(rho, rho_o):.1e} J {max_rel(J, J_o):.1e} K rows {err_k:.1e} "
-          f"E_J {ej_o:.10f} Eh, diff {ej - ej_o:.1e}")
+          f"E_J {ej_o:.10f} Eh, diff {ej - ej_o:.1e}; DF diagonal {err_d:.1e}")
 
 
 def test_c2_fp32_full(pkg, c2):

@@ -121,3 +121,33 @@ def test_every_j_out_width(pkg, naux):
     for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_J_OUT)):
         pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_J_OUT, t)
         assert max_rel(host(h.J(Dd)), J_ref) < TOL, t
+
+
+@pytest.mark.parametrize("nao,naux,seed,ld_pad", [(64, 256, 1, 0), (300, 77, 31, 0), (129, 40, 32, 3)])
+def test_df_diagonal(pkg, nao, naux, seed, ld_pad):
+    """The DF diagonal from the J pass-2 stream equals the oracle's
+    sum_P B[P,p]^2 (1e-12 relative: FP64 sums of positive terms), and J and
+    rho are bitwise those of dfjk_build_J."""
+    print(f"df diagonal nao={nao} naux={naux} ld_pad={ld_pad}", flush=True)
+    R, B, C = system(nao, naux, 4, seed, ld_pad)
+    D = 2 * C @ C.T
+    h = pkg.Handle(dev(B), nao)
+    Dd = dev(D)
+    npair = nao * (nao + 1) // 2
+    J0 = torch.empty((nao, nao), dtype=torch.float64, device="cuda")
+    J1 = torch.empty_like(J0)
+    r0 = torch.empty(naux, dtype=torch.float64, device="cuda")
+    r1 = torch.empty_like(r0)
+    dg = torch.empty(npair, dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J(h.h, Dd, J0, r0)
+    pkg.dfjk_build_J_diag(h.h, Dd, J1, r1, dg)
+    ref = oracle.df_diagonal(B, nao)
+    assert float(np.abs(host(dg) - ref).max() / ref.max()) < 1e-12
+    assert torch.equal(J0, J1) and torch.equal(r0, r1)
+    for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_J_OUT)):  # every pass-2 width
+        pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_J_OUT, t)
+        pkg.dfjk_build_J_diag(h.h, Dd, J1, r1, dg)
+        assert float(np.abs(host(dg) - ref).max() / ref.max()) < 1e-12, t
+    with pytest.raises(pkg.DFJKError):
+        pkg.dfjk_build_J_diag(h.h, Dd, J1, r1, None)
+    h.close()

@@ -123,3 +123,24 @@ def test_k16_exchange(pkg, dtype, bound, nao, naux, nocc, seed):
     for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_K16)):  # every GEMM1 tile
         pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_K16, t)
         assert max_rel(host(h.K(C=dev(C))), K_ref) < bound, t
+
+
+@pytest.mark.parametrize("dtype", [F32, BF16, F16])
+def test_reduced_df_diagonal(pkg, dtype):
+    """DF diagonal with B stored in FP32/BF16/FP16: FP64 sums of the exact
+    squares of the stored values, so it matches the oracle on the rounded B
+    to 1e-12; J is bitwise that of dfjk_build_J."""
+    nao, naux = 300, 77
+    R, B, C = system(nao, naux, 5, 31)
+    D = 2 * C @ C.T
+    Bq = QUANT[dtype](B)
+    h = pkg.Handle(gpu_quantize(pkg, B, dtype), nao, dtype=dtype)
+    Dd = dev(D)
+    J0 = h.J(Dd)
+    J1 = torch.empty_like(J0)
+    dg = torch.empty(nao * (nao + 1) // 2, dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J_diag(h.h, Dd, J1, None, dg)
+    ref = oracle.df_diagonal(Bq, nao)
+    assert float(np.abs(host(dg) - ref).max() / ref.max()) < 1e-12
+    assert torch.equal(J0, J1)
+    h.close()
