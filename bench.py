@@ -582,6 +582,22 @@ def main():
     res["j_with_df_diagonal"] = {"ms": jd_ms, "hbm_gbs": jbytes / jd_ms / 1e6,
                                  "overhead_vs_j": jd_ms / j_ms - 1.0}
     del dg
+    # J for 8 densities through one pair of passes over B
+    if dt_code == pkg.DFJK_F64:
+        nd = 8
+        Dm = Dd.unsqueeze(0).repeat(nd, 1, 1).contiguous()
+        Jm = torch.empty_like(Dm)
+        pkg.dfjk_build_J_multi(h.h, nd, Dm, Jm, None)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            pkg.dfjk_build_J_multi(h.h, nd, Dm, Jm, None)
+        e1.record()
+        torch.cuda.synchronize()
+        jm_ms = e0.elapsed_time(e1) / args.steps
+        res["j_8_densities"] = {"ms": jm_ms, "ms_per_density": jm_ms / nd, "speedup_vs_8_single": nd * j_ms / jm_ms,
+                                "b_stream_gbs": jbytes / jm_ms / 1e6}
+        del Dm, Jm
     res["measured_mfma_ceiling_tflops"] = {
         "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
         "bf16_16x16x32": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}

@@ -108,6 +108,19 @@ int dfjk_init(dfjk_handle* h, const void* B_dev, int dtype, int64_t nao, int64_t
 int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev);
 
 /*
+ * J for ndm densities (the paper's get_jk takes any number of density
+ * matrices, Sec. II): D_dev and J_dev hold ndm row-major nao x nao FP64
+ * matrices back to back, rho_dev (or NULL) ndm x naux.  With FP64 B both
+ * passes read B once for up to 8 densities at a time (each B element is
+ * multiplied with all of them), so ndm densities cost about ceil(ndm/8)
+ * single-density passes of HBM traffic; with reduced-precision B the
+ * densities are streamed one after another.  Each J equals dfjk_build_J's up
+ * to summation order (FP64).  The handle allocates its workspace on the first
+ * call.  Errors: DFJK_E_INVALID (ndm < 1, null D or J), as dfjk_build_J.
+ */
+int dfjk_build_J_multi(dfjk_handle h, int64_t ndm, const double* D_dev, double* J_dev, double* rho_dev);
+
+/*
  * dfjk_build_J plus the DF diagonal from the same pass over B:
  *   diag_dev[p(mu,nu)] = sum_P B[P, p(mu,nu)]^2,  p = max(mu,nu)(max+1)/2 + min,
  * the density-fitted (mu nu|mu nu), whose difference from the exact diagonal

@@ -142,6 +142,16 @@ int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_
     return j_build(h, D_dev, J_dev, rho_dev, nullptr);
 }
 
+int dfjk_build_J_multi(dfjk_handle h, int64_t ndm, const double* D_dev, double* J_dev, double* rho_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (ndm < 1 || !D_dev || !J_dev) {
+        set_error("dfjk_build_J_multi: ndm must be >= 1 and D, J non-null");
+        return DFJK_E_INVALID;
+    }
+    return j_build_multi(h, ndm, D_dev, J_dev, rho_dev);
+}
+
 int dfjk_build_J_diag(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev, double* diag_dev) {
     clear_error();
     if (int rc = check_handle(h)) return rc;
@@ -293,7 +303,8 @@ int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes) {
         set_error("dfjk_workspace_bytes: null output");
         return DFJK_E_INVALID;
     }
-    *bytes = h->dt.bytes + h->rho_part.bytes + h->rho.bytes + h->jpart.bytes + h->dpart.bytes + h->X.bytes +
+    *bytes = h->dt.bytes + h->rho_part.bytes + h->rho.bytes + h->jpart.bytes + h->dpart.bytes + h->mdt.bytes + h->mpart.bytes +
+             h->mrho.bytes + h->mjpart.bytes + h->X.bytes +
              h->kpart.bytes + h->ones.bytes + h->Cw.bytes + h->eig.bytes + h->Bdense.bytes;
     return DFJK_OK;
 }
@@ -376,6 +387,10 @@ void dfjk_destroy(dfjk_handle h) {
     h->rho.release();
     h->jpart.release();
     h->dpart.release();
+    h->mdt.release();
+    h->mpart.release();
+    h->mrho.release();
+    h->mjpart.release();
     h->X.release();
     h->kpart.release();
     h->ones.release();

@@ -75,6 +75,7 @@ struct dfjk_ctx {
     dfjk::DevBuf rho;       // naux
     dfjk::DevBuf jpart;     // j_splits x npair partial sums
     dfjk::DevBuf dpart;     // j_splits x npair partial sums of B^2 (DF diagonal, on request)
+    dfjk::DevBuf mdt, mpart, mrho, mjpart;  // several-density J workspace (on request)
     int j_chunks = 1, j_splits = 1;
 
     // K workspace
@@ -103,6 +104,7 @@ namespace dfjk {
 // J launchers (j_kernels.hip)
 int j_setup(dfjk_ctx* h);
 int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* diag);
+int j_build_multi(dfjk_ctx* h, int64_t ndm, const double* D, double* J, double* rho_out);
 int j_out_count();
 
 // K launchers (k_kernels.hip)

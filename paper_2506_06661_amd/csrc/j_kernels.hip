@@ -554,6 +554,193 @@ __global__ __launch_bounds__(kThreads) void jb_kernel(int kind, const MolDesc* _
     }
 }
 
+// ---------------------------------------------------------------- several densities
+// J for M densities from one pass over B per pass (FP64 B): pass 1 reads each
+// B element once for all M packed densities, pass 2 once for all M rho.
+constexpr int kMaxDm = 8;     // densities fused per pass
+constexpr int kRhoRowsM = 8;  // rows of B per workgroup in pass 1 (M/R packed-density loads per B element)
+
+__global__ __launch_bounds__(kThreads) void pack_density_m(const double* __restrict__ D, int64_t nao,
+                                                            int64_t npair, double* __restrict__ dt) {
+    const int64_t m = blockIdx.y;
+    pack_density_body(blockIdx.x, D + m * nao * nao, nao, dt + m * npair);
+}
+
+// part[m][P][c] = sum over chunk c of B[P,p] dt_m[p]
+template <int M, bool VEC>
+__global__ __launch_bounds__(kThreads) void j_rho_f64m(const double* __restrict__ B, int64_t ldB,
+                                                        int64_t naux, int64_t npair,
+                                                        const double* __restrict__ dt, int64_t chunk,
+                                                        int nchunk, double* __restrict__ part) {
+    constexpr int R = kRhoRowsM;
+    __shared__ double lds[4];
+    const int64_t P0 = (int64_t)blockIdx.x * R;
+    const int c = blockIdx.y;
+    const int64_t c0 = (int64_t)c * chunk;
+    const int64_t c1 = c0 + chunk < npair ? c0 + chunk : npair;
+    const double* rows[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t P = P0 + r < naux ? P0 + r : naux - 1;  // clamped rows are discarded below
+        rows[r] = B + P * ldB;
+    }
+    double acc[M][R];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[m][r] = 0.0;
+    if (VEC) {
+        int64_t p = c0 + 2 * (int64_t)threadIdx.x;
+        for (; p + 1 < c1; p += 2 * kThreads) {
+            d2 b[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) b[r] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(rows[r] + p));
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const d2 d = *reinterpret_cast<const d2*>(dt + m * npair + p);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    acc[m][r] = fma(b[r].x, d.x, acc[m][r]);
+                    acc[m][r] = fma(b[r].y, d.y, acc[m][r]);
+                }
+            }
+        }
+        if (p < c1) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const double d = dt[m * npair + p];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[m][r] = fma(rows[r][p], d, acc[m][r]);
+            }
+        }
+    } else {
+        for (int64_t p = c0 + threadIdx.x; p < c1; p += kThreads) {
+            double b[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) b[r] = __builtin_nontemporal_load(rows[r] + p);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const double d = dt[m * npair + p];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[m][r] = fma(b[r], d, acc[m][r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double sum = block_sum(acc[m][r], lds);
+            if (threadIdx.x == 0 && P0 + r < naux) part[(m * naux + P0 + r) * nchunk + c] = sum;
+        }
+}
+
+__global__ void j_rho_finish_m(const double* __restrict__ part, int64_t naux, int nchunk,
+                               double* __restrict__ rho, double* __restrict__ rho_out) {
+    const int64_t m = blockIdx.y;
+    rho_finish_body((int64_t)blockIdx.x * blockDim.x + threadIdx.x, part + m * naux * nchunk, naux, nchunk,
+                    rho + m * naux, rho_out ? rho_out + m * naux : nullptr);
+}
+
+// jpart[m][s][p] = sum over the row slice s of B[P,p] rho_m[P]; 1024 columns per workgroup
+template <int M, bool VEC>
+__global__ __launch_bounds__(kThreads) void j_out_f64m(const double* __restrict__ B, int64_t ldB,
+                                                        int64_t naux, int64_t npair,
+                                                        const double* __restrict__ rho, int64_t prows,
+                                                        int64_t nsplit, double* __restrict__ jpart) {
+    constexpr int U = 2;
+    constexpr int64_t COLS = (int64_t)kThreads * 2 * U;
+    const int s = blockIdx.y;
+    const int64_t P0 = (int64_t)s * prows;
+    const int64_t P1 = P0 + prows < naux ? P0 + prows : naux;
+    const int64_t base = (int64_t)blockIdx.x * COLS;
+    double acc[M][2 * U];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int u = 0; u < 2 * U; ++u) acc[m][u] = 0.0;
+    const int64_t col0 = base + 2 * (int64_t)threadIdx.x;
+    const bool full = base + COLS <= npair;
+    if (VEC && full) {
+        for (int64_t P = P0; P < P1; ++P) {
+            const double* row = B + P * ldB + col0;
+            d2 b[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) b[u] = __builtin_nontemporal_load(reinterpret_cast<const d2*>(row + u * 2 * kThreads));
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const double r = rho[m * naux + P];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    acc[m][2 * u] = fma(b[u].x, r, acc[m][2 * u]);
+                    acc[m][2 * u + 1] = fma(b[u].y, r, acc[m][2 * u + 1]);
+                }
+            }
+        }
+    } else {
+        for (int64_t P = P0; P < P1; ++P) {
+            const double* row = B + P * ldB;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int64_t col = col0 + u * 2 * kThreads + e;
+                    if (col < npair) {
+                        const double b = row[col];
+#pragma unroll
+                        for (int m = 0; m < M; ++m) acc[m][2 * u + e] = fma(b, rho[m * naux + P], acc[m][2 * u + e]);
+                    }
+                }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double* out = jpart + (m * nsplit + s) * npair;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int64_t col = col0 + u * 2 * kThreads + e;
+                if (col < npair) out[col] = acc[m][2 * u + e];
+            }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void j_finish_m(const double* __restrict__ jpart, int64_t npair,
+                                                        int nsplit, int64_t nao, double* __restrict__ J) {
+    const int64_t m = blockIdx.y;
+    j_finish_body(blockIdx.x, jpart + m * nsplit * npair, npair, nsplit, nao, J + m * nao * nao);
+}
+
+template <int M>
+void launch_j_multi(bool vec, dim3 g1, dim3 g2, hipStream_t st, const double* B, int64_t ldB, int64_t naux,
+                    int64_t npair, const double* dt, int64_t chunk, int nchunk, double* part,
+                    const double* rho, int64_t prows, int64_t nsplit, double* jpart, bool pass1) {
+    if (pass1) {
+        if (vec)
+            j_rho_f64m<M, true><<<g1, kThreads, 0, st>>>(B, ldB, naux, npair, dt, chunk, nchunk, part);
+        else
+            j_rho_f64m<M, false><<<g1, kThreads, 0, st>>>(B, ldB, naux, npair, dt, chunk, nchunk, part);
+    } else {
+        if (vec)
+            j_out_f64m<M, true><<<g2, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, nsplit, jpart);
+        else
+            j_out_f64m<M, false><<<g2, kThreads, 0, st>>>(B, ldB, naux, npair, rho, prows, nsplit, jpart);
+    }
+}
+
+void dispatch_j_multi(int M, bool vec, dim3 g1, dim3 g2, hipStream_t st, const double* B, int64_t ldB,
+                      int64_t naux, int64_t npair, const double* dt, int64_t chunk, int nchunk, double* part,
+                      const double* rho, int64_t prows, int64_t nsplit, double* jpart, bool pass1) {
+    switch (M) {
+#define DFJK_JM(k) \
+    case k: launch_j_multi<k>(vec, g1, g2, st, B, ldB, naux, npair, dt, chunk, nchunk, part, rho, prows, nsplit, jpart, pass1); break;
+        DFJK_JM(1) DFJK_JM(2) DFJK_JM(3) DFJK_JM(4) DFJK_JM(5) DFJK_JM(6) DFJK_JM(7) DFJK_JM(8)
+#undef DFJK_JM
+        default: break;
+    }
+}
+
 }  // namespace
 
 int j_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl) {
@@ -668,6 +855,69 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* di
     if (dpart) {
         diag_finish<<<dim3((unsigned)cdiv(h->npair, 256)), 256, 0, st>>>(dpart, h->npair, (int)splits, diag);
         DFJK_LAUNCH_CHECK("diag_finish");
+    }
+    h->prof.end(PH_J, st);
+    return DFJK_OK;
+}
+
+int j_build_multi(dfjk_ctx* h, int64_t ndm, const double* D, double* J, double* rho_out) {
+    const int64_t nao = h->nao, naux = h->naux, npair = h->npair;
+    if (h->dtype != DFJK_F64) {  // reduced B: one J stream per density
+        for (int64_t m = 0; m < ndm; ++m) {
+            int rc = j_build(h, D + m * nao * nao, J + m * nao * nao, rho_out ? rho_out + m * naux : nullptr,
+                             nullptr);
+            if (rc) return rc;
+        }
+        return DFJK_OK;
+    }
+    const hipStream_t st = h->stream;
+    const double* B = static_cast<const double*>(h->B);
+    const bool vec = (h->ldB % 2 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    const int64_t mmax = ndm < kMaxDm ? ndm : kMaxDm;
+    // pass 1 geometry: (8-row block, chunk) workgroups covering the chip several times
+    const int64_t rowblocks = cdiv(naux, kRhoRowsM);
+    int64_t nchunk = cdiv(4096, rowblocks);
+    const int64_t max_chunks = cdiv(npair, 2 * kThreads * 4);
+    if (nchunk > max_chunks) nchunk = max_chunks;
+    if (nchunk < 1) nchunk = 1;
+    int64_t chunk = cdiv(cdiv(npair, nchunk), 2) * 2;
+    // pass 2 geometry: 1024 columns per workgroup
+    int64_t nsplit;
+    j_out_geometry(h, 2, &nsplit);
+    const int64_t prows = cdiv(naux, nsplit);
+    int rc;
+    if ((rc = h->mdt.ensure(sizeof(double) * (size_t)(mmax * npair))) ||
+        (rc = h->mpart.ensure(sizeof(double) * (size_t)(mmax * naux * nchunk))) ||
+        (rc = h->mrho.ensure(sizeof(double) * (size_t)(mmax * naux))) ||
+        (rc = h->mjpart.ensure(sizeof(double) * (size_t)(mmax * nsplit * npair))))
+        return rc;
+    double* dt = static_cast<double*>(h->mdt.ptr);
+    double* part = static_cast<double*>(h->mpart.ptr);
+    double* rho = static_cast<double*>(h->mrho.ptr);
+    double* jpart = static_cast<double*>(h->mjpart.ptr);
+    const dim3 g1((unsigned)rowblocks, (unsigned)nchunk);
+    const dim3 g2((unsigned)cdiv(npair, (int64_t)kThreads * 4), (unsigned)nsplit);
+    h->prof.begin(PH_J, st);
+    for (int64_t m0 = 0; m0 < ndm; m0 += kMaxDm) {
+        const int M = (int)(ndm - m0 < kMaxDm ? ndm - m0 : kMaxDm);
+        pack_density_m<<<dim3((unsigned)nao, (unsigned)M), kThreads, 0, st>>>(D + m0 * nao * nao, nao, npair, dt);
+        DFJK_LAUNCH_CHECK("pack_density_m");
+        h->prof.begin(PH_J_RHO, st);
+        dispatch_j_multi(M, vec, g1, g2, st, B, h->ldB, naux, npair, dt, chunk, (int)nchunk, part, rho, prows,
+                         nsplit, jpart, true);
+        h->prof.end(PH_J_RHO, st);
+        DFJK_LAUNCH_CHECK("j_rho_f64m");
+        j_rho_finish_m<<<dim3((unsigned)cdiv(naux, 256), (unsigned)M), 256, 0, st>>>(
+            part, naux, (int)nchunk, rho, rho_out ? rho_out + m0 * naux : nullptr);
+        DFJK_LAUNCH_CHECK("j_rho_finish_m");
+        h->prof.begin(PH_J_OUT, st);
+        dispatch_j_multi(M, vec, g1, g2, st, B, h->ldB, naux, npair, dt, chunk, (int)nchunk, part, rho, prows,
+                         nsplit, jpart, false);
+        h->prof.end(PH_J_OUT, st);
+        DFJK_LAUNCH_CHECK("j_out_f64m");
+        j_finish_m<<<dim3((unsigned)nao, (unsigned)M), kThreads, 0, st>>>(jpart, npair, (int)nsplit, nao,
+                                                                           J + m0 * nao * nao);
+        DFJK_LAUNCH_CHECK("j_finish_m");
     }
     h->prof.end(PH_J, st);
     return DFJK_OK;

@@ -64,6 +64,7 @@ def lib():
         L.dfjk_init.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i64, i64, vp, ctypes.POINTER(Options)]
         L.dfjk_build_J.argtypes = [vp, vp, vp, vp]
         L.dfjk_build_J_diag.argtypes = [vp, vp, vp, vp, vp]
+        L.dfjk_build_J_multi.argtypes = [vp, i64, vp, vp, vp]
         L.dfjk_build_K.argtypes = [vp, vp, i64, vp, vp]
         L.dfjk_build_K_factored.argtypes = [vp, vp, i64, vp, dbl, vp]
         L.dfjk_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -163,6 +164,10 @@ def dfjk_init(B, dtype: int, nao: int, naux: int, ldB: int, stream=None, opts: O
 
 def dfjk_build_J(h, D, J, rho=None) -> int:
     return _check("dfjk_build_J", lib().dfjk_build_J(h, _ptr(D), _ptr(J), _ptr(rho)))
+
+
+def dfjk_build_J_multi(h, ndm: int, D, J, rho=None) -> int:
+    return _check("dfjk_build_J_multi", lib().dfjk_build_J_multi(h, ndm, _ptr(D), _ptr(J), _ptr(rho)))
 
 
 def dfjk_build_J_diag(h, D, J, rho, diag) -> int:

@@ -133,6 +133,17 @@ def test_c2_fp64_full(pkg, c2):
     d_o = oracle.df_diagonal(B, cfg.nao)
     err_d = float(np.abs(host(dg) - d_o).max() / d_o.max())
     assert err_d < 1e-12 and np.array_equal(host(Jd), J)
+    # two densities through one pass: D and a random symmetric matrix
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((cfg.nao, cfg.nao))
+    Ds = np.stack([D, A + A.T])
+    h = pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao)
+    Jm = torch.empty((2, cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J_multi(h.h, 2, torch.from_numpy(Ds).cuda(), Jm, None)
+    h.close()
+    Jm = host(Jm)
+    assert max_rel(Jm[0], J_o) < 1e-10
+    assert max_rel(Jm[1], oracle.J(B, cfg.nao, Ds[1])) < 1e-10
     print(f"C2 FP64: rho {max_rel(rho, rho_o):.1e} J {max_rel(J, J_o):.1e} K rows {err_k:.1e} "
           f"E_J {ej_o:.10f} Eh, diff {ej - ej_o:.1e}; DF diagonal {err_d:.1e}")
 

@@ -151,3 +151,28 @@ def test_df_diagonal(pkg, nao, naux, seed, ld_pad):
     with pytest.raises(pkg.DFJKError):
         pkg.dfjk_build_J_diag(h.h, Dd, J1, r1, None)
     h.close()
+
+
+@pytest.mark.parametrize("ndm", [1, 3, 8, 11])
+@pytest.mark.parametrize("nao,naux,seed,ld_pad", [(300, 77, 31, 0), (129, 40, 32, 3)])
+def test_J_several_densities(pkg, ndm, nao, naux, seed, ld_pad):
+    """dfjk_build_J_multi: every J (and rho) equals the oracle's for its own
+    density (non-symmetric densities included); 11 densities run as 8 + 3."""
+    print(f"J multi ndm={ndm} nao={nao} naux={naux}", flush=True)
+    R, B, C = system(nao, naux, 4, seed, ld_pad)
+    rng = np.random.default_rng(seed + ndm)
+    Ds = rng.standard_normal((ndm, nao, nao))
+    Ds[0] = 2 * C @ C.T
+    h = pkg.Handle(dev(B), nao)
+    J = torch.empty((ndm, nao, nao), dtype=torch.float64, device="cuda")
+    rho = torch.empty((ndm, naux), dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J_multi(h.h, ndm, dev(Ds), J, rho)
+    Jh, rh = host(J), host(rho)
+    for m in range(ndm):
+        J_ref, r_ref = oracle.J(B, nao, Ds[m], return_rho=True)
+        assert max_rel(Jh[m], J_ref) < TOL, m
+        assert max_rel(rh[m], r_ref) < TOL, m
+    J1 = torch.empty_like(J)
+    pkg.dfjk_build_J_multi(h.h, ndm, dev(Ds), J1, None)
+    assert torch.equal(J, J1)  # deterministic
+    h.close()

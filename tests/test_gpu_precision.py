@@ -144,3 +144,18 @@ def test_reduced_df_diagonal(pkg, dtype):
     assert float(np.abs(host(dg) - ref).max() / ref.max()) < 1e-12
     assert torch.equal(J0, J1)
     h.close()
+
+
+def test_reduced_several_densities(pkg):
+    """Reduced B streams the densities one after another: each J is bitwise
+    dfjk_build_J's."""
+    nao, naux = 129, 40
+    R, B, C = system(nao, naux, 5, 32)
+    rng = np.random.default_rng(5)
+    Ds = rng.standard_normal((3, nao, nao))
+    h = pkg.Handle(gpu_quantize(pkg, B, BF16), nao, dtype=BF16)
+    J = torch.empty((3, nao, nao), dtype=torch.float64, device="cuda")
+    pkg.dfjk_build_J_multi(h.h, 3, dev(Ds), J, None)
+    for m in range(3):
+        assert torch.equal(J[m], h.J(dev(Ds[m])))
+    h.close()
