@@ -8,6 +8,7 @@ the only thing both sides use is the input generator in ``synth``.
 Contents, each following the passage it cites:
 
 * ``df_diagonal`` -- sum_P T[P, mu nu]^2 per packed pair (Sec. IV.C.2).
+* ``form_B`` -- T = L^-1 Q from the metric Cholesky factor (Sec. IV.C.2).
 * ``rho``, ``J``, ``K_C``, ``K_D``, ``K_C_rows`` -- the J/K contractions of
   Sec. IV.C.2, Eq. eq:df:eri, written as plain loops in ``oracle.c``.
 * ``energies`` -- E_J = 1/2 sum_P rho_P^2 = 1/2 tr(DJ) and E_K = -1/4 tr(DK).
@@ -146,6 +147,16 @@ def K_C_rows(Bsel: np.ndarray, C: np.ndarray) -> np.ndarray:
     if lib().oracle_K_C_rows(_dp(Bsel), nsel, nao, naux, _dp(C), C.shape[1], _dp(out)) != 0:
         raise MemoryError("oracle_K_C_rows")
     return out
+
+
+def form_B(M: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """The 3-index factor of Eq. eq:df:eri: M = L L^T (Cholesky of the
+    auxiliary metric, lower L), T = L^-1 Q with Q the 3-index integrals
+    (P|mu nu), one column per packed pair (Sec. IV.C.2)."""
+    import scipy.linalg
+
+    L = np.linalg.cholesky(_f64(M))
+    return scipy.linalg.solve_triangular(L, _f64(Q), lower=True)
 
 
 def df_diagonal(B: np.ndarray, nao: int) -> np.ndarray:

@@ -44,6 +44,7 @@ STREAM_H_OFF = 5
 STREAM_JITTER = 6
 STREAM_BATCH = 7
 STREAM_MLP = 8
+STREAM_METRIC = 9
 
 
 def build() -> str:
@@ -195,6 +196,13 @@ def B_cols(seed: int, R: np.ndarray, naux: int, cols) -> np.ndarray:
     lib().synth_B_cols(seed, R.shape[0], _dp(R), naux,
                        cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cols.size, _dp(out))
     return out
+
+
+def metric(seed: int, naux: int, shift: float = 0.05) -> np.ndarray:
+    """Synthetic symmetric positive definite auxiliary metric
+    M = G G^T / naux + shift * I with G ~ N(0,1) (naux x naux)."""
+    G = normal(seed, STREAM_METRIC, naux * naux).reshape(naux, naux)
+    return np.ascontiguousarray(G @ G.T / naux + shift * np.eye(naux))
 
 
 def C_occ(seed: int, nao: int, nocc: int) -> np.ndarray:

@@ -98,6 +98,25 @@ def test_df_diagonal_bruteforce(c1):
     assert np.array_equal(oracle.df_diagonal(Bpad, nao), d)
 
 
+def test_form_B_identities():
+    """T = L^-1 Q reproduces the DF integrals (mu nu|ka la) = Q^T M^-1 Q
+    (checked with a general solve, not a Cholesky), L L^T = M, and the special
+    metrics M = I (T = Q) and M diagonal (T = Q / sqrt(diag M))."""
+    naux, ncol = 37, 50
+    M = synth.metric(3, naux)
+    rng = np.random.default_rng(4)
+    Q = rng.standard_normal((naux, ncol))
+    T = oracle.form_B(M, Q)
+    assert rel(T.T @ T, Q.T @ np.linalg.solve(M, Q)) < 1e-12
+    L = np.linalg.cholesky(M)
+    assert rel(L @ T, Q) < 1e-13
+    assert np.array_equal(oracle.form_B(np.eye(naux), Q), Q)
+    d = rng.uniform(0.5, 2.0, naux)
+    assert rel(oracle.form_B(np.diag(d), Q), Q / np.sqrt(d)[:, None]) < 1e-15
+    # the synthetic metric is symmetric positive definite
+    assert np.allclose(M, M.T) and np.linalg.eigvalsh(M).min() > 0.04
+
+
 def test_closed_form_rank_one():
     """naux = 1, B_1 = u u^T: J = K = (u^T D u) u u^T."""
     rng = np.random.default_rng(1)
