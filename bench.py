@@ -420,16 +420,52 @@ def bench_c5mp(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_bform(args):
+    """B = L^-1 Q at naux=4096 and 524800 columns (nao=1024 packed): the
+    metric Cholesky and the forward substitution on the GPU, FP64."""
+    import torch
+
+    import paper_2506_06661_amd as pkg
+    import synth
+
+    cfg = synth.C2
+    R = synth.positions(cfg)
+    Q = torch.from_numpy(synth.B_full(cfg.seed, R, cfg.naux)).cuda()
+    M = torch.from_numpy(synth.metric(cfg.seed, cfg.naux)).cuda()
+    # Cholesky naux^3/3 flop, substitution naux^2 flop per column
+    flops = cfg.naux ** 3 / 3.0 + float(cfg.naux) ** 2 * cfg.npair
+    times = []
+    for it in range(args.warmup + args.steps):
+        Md, Qd = M.clone(), Q.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pkg.dfjk_form_B(cfg.naux, cfg.npair, Md, Qd, cfg.npair)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            times.append((time.perf_counter() - t0) * 1e3)
+        del Md, Qd
+    ms = float(np.median(times))
+    res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
+           "value": flops / ms / 1e9, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"3-index factor B = L^-1 Q: naux={cfg.naux}, {cfg.npair} columns, "
+                                  f"synthetic SPD metric, FP64 (Cholesky + forward substitution)",
+                      "naux": cfg.naux, "ncol": cfg.npair},
+           "flop_model": "naux^3/3 (Cholesky) + naux^2 * ncol (substitution)"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5mp"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5mp", "bform"],
                     help="c2: nao=1024 FP64 (+FP32) single builds (default); c3: nao=2048 BF16/FP16; "
                          "c4: 256-molecule batch; c5: learned-guess SCF experiment; "
-                         "c5mp: mixed-precision SCF")
+                         "c5mp: mixed-precision SCF; bform: B = L^-1 Q on the GPU")
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -471,6 +507,8 @@ def main():
         return bench_c5(args)
     if args.workload == "c5mp":
         return bench_c5mp(args)
+    if args.workload == "bform":
+        return bench_bform(args)
     cfg = synth.C2
     t0 = time.time()
     R = synth.positions(cfg)

@@ -108,6 +108,24 @@ int dfjk_init(dfjk_handle* h, const void* B_dev, int dtype, int64_t nao, int64_t
 int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev);
 
 /*
+ * The 3-index factor of Eq. eq:df:eri (Sec. IV.C.2): with the auxiliary
+ * metric M = L L^T (Cholesky, lower L) and the 3-index integrals Q = (P|mu
+ * nu), B = L^-1 Q.  No handle needed.
+ *   naux    auxiliary functions; ncol columns of Q (npair for a packed B).
+ *   M_dev   device, naux x naux row-major FP64, symmetric positive definite;
+ *           overwritten by L (strict upper triangle set to zero).
+ *   Q_dev   device, naux x ldQ row-major FP64; columns < ncol overwritten by
+ *           B (the result is directly a B for dfjk_init, dtype DFJK_F64).
+ *   stream  hipStream_t or NULL; the call waits for the stream at the end.
+ * Blocked by 64: Cholesky with FP64 matrix-core trailing updates, then
+ * forward substitution with matrix-core updates; deterministic.
+ * Errors: DFJK_E_INVALID, DFJK_E_NO_DEVICE, DFJK_E_OOM, DFJK_E_HIP,
+ * DFJK_E_NONFINITE (M not positive definite; M and Q then hold partial
+ * results).
+ */
+int dfjk_form_B(int64_t naux, int64_t ncol, double* M_dev, double* Q_dev, int64_t ldQ, void* stream);
+
+/*
  * J for ndm densities (the paper's get_jk takes any number of density
  * matrices, Sec. II): D_dev and J_dev hold ndm row-major nao x nao FP64
  * matrices back to back, rho_dev (or NULL) ndm x naux.  With FP64 B both

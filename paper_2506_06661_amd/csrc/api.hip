@@ -142,6 +142,21 @@ int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_
     return j_build(h, D_dev, J_dev, rho_dev, nullptr);
 }
 
+int dfjk_form_B(int64_t naux, int64_t ncol, double* M_dev, double* Q_dev, int64_t ldQ, void* stream) {
+    clear_error();
+    if (naux < 1 || ncol < 1 || ldQ < ncol || !M_dev || !Q_dev) {
+        set_error("dfjk_form_B: need naux >= 1, ncol >= 1, ldQ >= ncol and non-null M, Q");
+        return DFJK_E_INVALID;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        set_error("dfjk_form_B: no HIP device available");
+        return DFJK_E_NO_DEVICE;
+    }
+    return form_B(naux, ncol, M_dev, Q_dev, ldQ, (hipStream_t)stream);
+}
+
 int dfjk_build_J_multi(dfjk_handle h, int64_t ndm, const double* D_dev, double* J_dev, double* rho_dev) {
     clear_error();
     if (int rc = check_handle(h)) return rc;

@@ -105,6 +105,7 @@ namespace dfjk {
 int j_setup(dfjk_ctx* h);
 int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* diag);
 int j_build_multi(dfjk_ctx* h, int64_t ndm, const double* D, double* J, double* rho_out);
+int form_B(int64_t naux, int64_t ncol, double* M, double* Q, int64_t ldQ, hipStream_t st);
 int j_out_count();
 
 // K launchers (k_kernels.hip)

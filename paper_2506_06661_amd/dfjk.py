@@ -65,6 +65,7 @@ def lib():
         L.dfjk_build_J.argtypes = [vp, vp, vp, vp]
         L.dfjk_build_J_diag.argtypes = [vp, vp, vp, vp, vp]
         L.dfjk_build_J_multi.argtypes = [vp, i64, vp, vp, vp]
+        L.dfjk_form_B.argtypes = [i64, i64, vp, vp, i64, vp]
         L.dfjk_build_K.argtypes = [vp, vp, i64, vp, vp]
         L.dfjk_build_K_factored.argtypes = [vp, vp, i64, vp, dbl, vp]
         L.dfjk_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -164,6 +165,11 @@ def dfjk_init(B, dtype: int, nao: int, naux: int, ldB: int, stream=None, opts: O
 
 def dfjk_build_J(h, D, J, rho=None) -> int:
     return _check("dfjk_build_J", lib().dfjk_build_J(h, _ptr(D), _ptr(J), _ptr(rho)))
+
+
+def dfjk_form_B(naux: int, ncol: int, M, Q, ldQ: int, stream=None) -> int:
+    """B = L^-1 Q in place of Q, L = Cholesky factor of M (M overwritten)."""
+    return _check("dfjk_form_B", lib().dfjk_form_B(naux, ncol, _ptr(M), _ptr(Q), ldQ, _stream(stream)))
 
 
 def dfjk_build_J_multi(h, ndm: int, D, J, rho=None) -> int:

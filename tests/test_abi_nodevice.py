@@ -44,6 +44,8 @@ def test_invalid_arguments(L):
     assert L.dfjk_build_J(None, fake, fake, None) == -1
     assert L.dfjk_build_J_diag(None, fake, fake, None, fake) == -1
     assert L.dfjk_build_J_multi(None, 2, fake, fake, None) == -1
+    assert L.dfjk_form_B(0, 5, fake, fake, 5, None) == -1
+    assert L.dfjk_form_B(4, 5, fake, fake, 4, None) == -1  # ldQ < ncol
     assert L.dfjk_build_K(None, fake, 3, None, fake) == -1
     assert L.dfjk_build_K_factored(None, fake, 3, None, ctypes.c_double(1.0), fake) == -1
     n = ctypes.c_size_t()

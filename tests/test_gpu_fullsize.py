@@ -171,6 +171,24 @@ def test_c2_fp32_full(pkg, c2):
           f"(i) {err_i:.1e}")
 
 
+def test_c2_form_B(pkg, c2):
+    """B = L^-1 Q at naux=4096 with 524800 columns (the lattice-decay B of
+    this workload standing in for the 3-index integrals Q, a synthetic SPD
+    metric): sampled columns against the oracle (columns are independent)."""
+    cfg, R, B, C, D = c2
+    M = synth.metric(cfg.seed, cfg.naux)
+    Md = torch.from_numpy(M).cuda()
+    Qd = torch.from_numpy(B).cuda()
+    pkg.dfjk_form_B(cfg.naux, cfg.npair, Md, Qd, cfg.npair)
+    cols = np.array([0, 1, 2, 1000, 65535, 262144, cfg.npair - 2, cfg.npair - 1])
+    got = host(Qd[:, torch.from_numpy(cols).cuda()])
+    del Qd
+    ref = oracle.form_B(M, B[:, cols])
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    assert err < 1e-10, err
+    print(f"C2 form_B: sampled columns {err:.1e}")
+
+
 # ---------------------------------------------------------------- C3 sizes
 @pytest.fixture(scope="module")
 def c3(pkg):
