@@ -420,6 +420,39 @@ def bench_c5mp(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_lrdf(args):
+    """The long-range-DF shape: nao=1024 (the lattice of the nao=1024 workload),
+    naux = 103 (about nao/10), nocc=200, FP64 B; one J and one K per step."""
+    import torch
+
+    import paper_2506_06661_amd as pkg
+    import synth
+
+    cfg = synth.C2
+    naux = 103
+    R = synth.positions(cfg)
+    C = synth.C_occ(cfg.seed, cfg.nao, cfg.nocc)
+    Bd = torch.from_numpy(synth.B_rows(cfg.seed, R, 0, naux)).cuda()
+    Cd = torch.from_numpy(C).cuda()
+    Dd = 2.0 * Cd @ Cd.T
+    h = pkg.Handle(Bd, cfg.nao)
+    lcfg = synth.Config("lrdf", cfg.nao, naux, cfg.nocc, cfg.seed)
+    r = time_steps(pkg, h, Dd, Cd, lcfg, args.steps, args.warmup)
+    h.close()
+    ph = r["phase_ms"]
+    g1, sy = k_flops(naux, cfg.nao, cfg.nocc)
+    jbytes = 2.0 * naux * cfg.npair * 8
+    res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
+           "value": (g1 + sy) / ph["K"] / 1e9, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"long-range DF shape: nao={cfg.nao}, naux={naux}, nocc={cfg.nocc}, FP64 B",
+                      "nao": cfg.nao, "naux": naux, "nocc": cfg.nocc},
+           "j_hbm_gbs": jbytes / ph["J"] / 1e6, "phase_ms": ph,
+           "k_gemm1_tflops": g1 / ph["K_gemm1"] / 1e9, "k_syrk_tflops": sy / ph["K_syrk"] / 1e9}
+    print(json.dumps(res), flush=True)
+
+
 def bench_bform(args):
     """B = L^-1 Q at naux=4096 and 524800 columns (nao=1024 packed): the
     metric Cholesky and the forward substitution on the GPU, FP64."""
@@ -462,10 +495,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5mp", "bform"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "c5mp", "bform", "lrdf"],
                     help="c2: nao=1024 FP64 (+FP32) single builds (default); c3: nao=2048 BF16/FP16; "
                          "c4: 256-molecule batch; c5: learned-guess SCF experiment; "
-                         "c5mp: mixed-precision SCF; bform: B = L^-1 Q on the GPU")
+                         "c5mp: mixed-precision SCF; bform: B = L^-1 Q on the GPU; "
+                         "lrdf: naux = nao/10")
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
@@ -509,6 +543,8 @@ def main():
         return bench_c5mp(args)
     if args.workload == "bform":
         return bench_bform(args)
+    if args.workload == "lrdf":
+        return bench_lrdf(args)
     cfg = synth.C2
     t0 = time.time()
     R = synth.positions(cfg)

@@ -176,3 +176,19 @@ def test_J_several_densities(pkg, ndm, nao, naux, seed, ld_pad):
     pkg.dfjk_build_J_multi(h.h, ndm, dev(Ds), J1, None)
     assert torch.equal(J, J1)  # deterministic
     h.close()
+
+
+@pytest.mark.slow
+def test_long_range_df_shape(pkg):
+    """naux ~ nao/10 at nao=1024 (the long-range-DF shape): J and K against
+    the oracle in full."""
+    cfg = synth.C2
+    naux = 103
+    R = synth.positions(cfg)
+    B = synth.B_rows(cfg.seed, R, 0, naux)
+    C = synth.C_occ(cfg.seed, cfg.nao, cfg.nocc)
+    D = 2 * C @ C.T
+    h = pkg.Handle(dev(B), cfg.nao)
+    assert max_rel(host(h.J(dev(D))), oracle.J(B, cfg.nao, D)) < TOL
+    assert max_rel(host(h.K(C=dev(C))), oracle.K_C(B, cfg.nao, C)) < TOL
+    h.close()
