@@ -201,16 +201,20 @@ __device__ inline int64_t xcd_logical(int64_t hw, int64_t nblk) {
 
 // X[(P*ncol + i)*ldx + mu] = sum_nu C[nu][i] B_P[nu][mu]
 // 1-D grid of nib * nmb * naux blocks; logical id -> (i block fastest, mu block, P)
+// Columns [ioff, iend) of the ncol orbital columns (a launch may cover part of
+// them with one tile and the rest with another).
 template <typename T, typename TS, int NI, int WM>
 __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
-                                    T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb) {
+                                    T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb,
+                                    int64_t ioff = 0, int64_t iend = -1) {
     constexpr int BI = 16 * NI, BM = 64 * WM;
+    if (iend < 0) iend = ncol;
     __shared__ T sC[2][KC][g1_pitch_c<T, TS, NI, WM>()];
     __shared__ T sB[2][KC][g1_pitch_b<T, TS, NI, WM>()];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
-    const int64_t i0 = ib * BI, mu0 = mb * BM;
+    const int64_t i0 = ioff + ib * BI, mu0 = mb * BM;
     const TS* Bp = B + P * ldB;
 
     typename Mma<T>::acc_t acc[NI][WM];
@@ -222,7 +226,7 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
     const int64_t nchunks = cdiv(nao, KC);
     G1Stage<T, NI, WM> st;
     G1Addr<NI, WM> ad;
-    g1_addr_init<NI, WM>(ad, nao, ldc, ncol, mu0, i0, tid);
+    g1_addr_init<NI, WM>(ad, nao, ldc, iend, mu0, i0, tid);
     g1_load<T, TS, NI, WM>(st, ad, Bp, nao, C, 0, mu0, tid);
     g1_store<T, TS, NI, WM>(st, sC[0], sB[0], KC <= mu0, tid);
     __syncthreads();
@@ -258,7 +262,7 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = i0 + ti * 16 + Mma<T>::row(lane, r);
                 const int64_t mu = mu0 + wave * 16 * WM + tj * 16 + (lane & 15);
-                if (i < ncol && mu < nao) X[(P * ncol + i) * ldx + mu] = acc[ti][tj][r];
+                if (i < iend && mu < nao) X[(P * ncol + i) * ldx + mu] = acc[ti][tj][r];
             }
 }
 
@@ -266,9 +270,9 @@ template <typename T, typename TS, int NI, int WM>
 __global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                                      const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                                      T* __restrict__ X, int64_t ldx, int64_t nib,
-                                                     int64_t nmb, int64_t nblk) {
+                                                     int64_t nmb, int64_t nblk, int64_t ioff, int64_t iend) {
     k_gemm1_body<T, TS, NI, WM>(xcd_logical(blockIdx.x, nblk), B, ldB, nao, C, ldc, ncol, X, ldx, nib,
-                                nmb);
+                                nmb, ioff, iend);
 }
 
 // ---------------------------------------------------------------- GEMM2 (SYRK)
@@ -420,12 +424,13 @@ __global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ 
 }
 
 template <typename T, typename TS, int NI, int WM>
-int launch_gemm1(const dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx) {
-    const int64_t nib = cdiv(ncol, 16 * NI), nmb = cdiv(h->nao, 64 * WM);
+int launch_gemm1(const dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx, int64_t ioff,
+                 int64_t iend) {
+    const int64_t nib = cdiv(iend - ioff, 16 * NI), nmb = cdiv(h->nao, 64 * WM);
     const int64_t nblk = nib * nmb * h->naux;
     k_gemm1<T, TS, NI, WM><<<dim3((unsigned)nblk), kThreads, 0, h->stream>>>(
         static_cast<const TS*>(h->B), h->ldB, h->nao, static_cast<const T*>(C), ncol, ncol,
-        static_cast<T*>(X), ldx, nib, nmb, nblk);
+        static_cast<T*>(X), ldx, nib, nmb, nblk, ioff, iend);
     DFJK_LAUNCH_CHECK("k_gemm1");
     return DFJK_OK;
 }
@@ -433,7 +438,7 @@ int launch_gemm1(const dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_
 // Compiled GEMM1 tiles: (NI, WM) = (i tiles of 16, mu tiles of 16 per wave),
 // one launcher per B storage type (FP64 on the FP64 matrix cores; FP32, BF16
 // and FP16 dequantised exactly on load and run on the FP32 matrix cores).
-typedef int (*G1Launch)(const dfjk_ctx*, const void*, int64_t, void*, int64_t);
+typedef int (*G1Launch)(const dfjk_ctx*, const void*, int64_t, void*, int64_t, int64_t, int64_t);
 struct G1Tile {
     int ni, wm;
     G1Launch by_dtype[4];  // indexed by dfjk_dtype
@@ -447,7 +452,7 @@ struct G1Tile {
     }
 const G1Tile kG1Tiles[] = {
     G1T(1, 2), G1T(2, 2), G1T(3, 2), G1T(4, 2), G1T(5, 2), G1T(6, 2),
-    G1T(7, 2), G1T(8, 2), G1T(13, 1), G1T(4, 4), G1T(7, 1), G1T(5, 1),
+    G1T(7, 2), G1T(8, 2), G1T(13, 1), G1T(4, 4), G1T(7, 1), G1T(5, 1), G1T(6, 1),
 };
 #undef G1T
 constexpr int kNumG1Tiles = sizeof(kG1Tiles) / sizeof(kG1Tiles[0]);
@@ -480,6 +485,37 @@ int pick_g1_tile(int64_t ncol, bool f32 = false) {
     return best;
 }
 
+// Default for the single build: one tile, or (FP64) the first columns with the
+// (7,1) tile and the remainder with the narrowest one-wave-row tile that
+// covers it, when that pads fewer columns (nocc=200: 112 + 96 = 208 columns
+// computed instead of 224).
+struct G1Split {
+    int t0, t1;
+    int64_t n0;  // columns [0, n0) with tile t0, [n0, ncol) with t1
+};
+inline int g1_tile_index(int ni, int wm) {
+    for (int t = 0; t < kNumG1Tiles; ++t)
+        if (kG1Tiles[t].ni == ni && kG1Tiles[t].wm == wm) return t;
+    return -1;
+}
+G1Split pick_g1_split(int64_t ncol, bool f32) {
+    const int single = pick_g1_tile(ncol, f32);
+    G1Split sp{single, single, ncol};
+    if (f32) return sp;
+    const int64_t w = 16 * kG1Tiles[single].ni;
+    const int64_t padded_single = cdiv(ncol, w) * w;
+    const int t7 = g1_tile_index(7, 1);
+    const int64_t n0 = (ncol / 112) * 112, rest = ncol - n0;
+    if (t7 < 0 || n0 == 0 || rest == 0) return sp;
+    for (int ni : {5, 6, 7}) {  // narrowest tile covering the rest
+        const int t = g1_tile_index(ni, 1);
+        if (t < 0 || 16 * ni < rest) continue;
+        if (n0 + 16 * ni < padded_single) sp = G1Split{t7, t, n0};
+        break;
+    }
+    return sp;
+}
+
 template <typename T>
 int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, double scale, double* K) {
     const int64_t ldx = h->nao;
@@ -490,9 +526,13 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
 
     h->prof.begin(PH_K, h->stream);
     h->prof.begin(PH_K_GEMM1, h->stream);
-    const int tile = h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles ? h->g1_tile
-                                                                  : pick_g1_tile(ncol, sizeof(T) == 4);
-    rc = kG1Tiles[tile].by_dtype[h->dtype](h, C, ncol, X, ldx);
+    if (h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles) {
+        rc = kG1Tiles[h->g1_tile].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, ncol);
+    } else {
+        G1Split sp = pick_g1_split(ncol, sizeof(T) == 4);
+        rc = kG1Tiles[sp.t0].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, sp.n0);
+        if (!rc && sp.n0 < ncol) rc = kG1Tiles[sp.t1].by_dtype[h->dtype](h, C, ncol, X, ldx, sp.n0, ncol);
+    }
     h->prof.end(PH_K_GEMM1, h->stream);
     if (rc) return rc;
 
@@ -584,7 +624,8 @@ int launch_kb_gemm1(hipStream_t st, int dtype, const MolDesc* mols, const PhaseL
 typedef int (*KbLaunch)(hipStream_t, int, const MolDesc*, const PhaseList&);
 #define KBT(a, b) launch_kb_gemm1<a, b>
 const KbLaunch kKbTiles[] = {KBT(1, 2), KBT(2, 2), KBT(3, 2), KBT(4, 2), KBT(5, 2), KBT(6, 2),
-                             KBT(7, 2), KBT(8, 2), KBT(13, 1), KBT(4, 4), KBT(7, 1), KBT(5, 1)};
+                             KBT(7, 2), KBT(8, 2), KBT(13, 1), KBT(4, 4), KBT(7, 1), KBT(5, 1),
+                             KBT(6, 1)};
 #undef KBT
 static_assert(sizeof(kKbTiles) / sizeof(kKbTiles[0]) == kNumG1Tiles, "tile tables differ");
 

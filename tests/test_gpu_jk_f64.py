@@ -192,3 +192,18 @@ def test_long_range_df_shape(pkg):
     assert max_rel(host(h.J(dev(D))), oracle.J(B, cfg.nao, D)) < TOL
     assert max_rel(host(h.K(C=dev(C))), oracle.K_C(B, cfg.nao, C)) < TOL
     h.close()
+
+
+@pytest.mark.parametrize("nocc", [113, 150, 200, 230])
+def test_gemm1_column_split(pkg, nocc):
+    """The default FP64 exchange covers the first columns with one tile and
+    the rest with another when that pads less (nocc=200: 112 + 96): K
+    matches the oracle and the single-tile result."""
+    nao, naux = 256, 12
+    R, B, C = system(nao, naux, nocc, 40 + nocc)
+    h = pkg.Handle(dev(B), nao)
+    K = host(h.K(C=dev(C)))
+    assert max_rel(K, oracle.K_C(B, nao, C)) < TOL
+    pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_GEMM1, 10)  # the (7,1) tile alone
+    assert max_rel(host(h.K(C=dev(C))), K) < 1e-13
+    h.close()
