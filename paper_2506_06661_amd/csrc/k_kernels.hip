@@ -452,10 +452,11 @@ struct G1Tile {
     }
 const G1Tile kG1Tiles[] = {
     G1T(1, 2), G1T(2, 2), G1T(3, 2), G1T(4, 2), G1T(5, 2), G1T(6, 2),
-    G1T(7, 2), G1T(8, 2), G1T(13, 1), G1T(4, 4), G1T(7, 1), G1T(5, 1), G1T(6, 1),
+    G1T(7, 2), G1T(8, 2), G1T(13, 1), G1T(4, 4), G1T(7, 1), G1T(5, 1), G1T(6, 1), G1T(3, 1),
 };
 #undef G1T
 constexpr int kNumG1Tiles = sizeof(kG1Tiles) / sizeof(kG1Tiles[0]);
+constexpr int kFirstRestTile = 12;  // (6,1) and (3,1): defaults only for the rest of a split
 
 // FP64 -> FP32 copy of C (one rounding per element).
 __global__ void to_f32(const double* __restrict__ x, int64_t n, float* __restrict__ y) {
@@ -472,7 +473,7 @@ __global__ void to_f32(const double* __restrict__ x, int64_t n, float* __restric
 int pick_g1_tile(int64_t ncol, bool f32 = false) {
     int best = 0;
     double best_cost = 1e300;
-    for (int t = 0; t < kNumG1Tiles; ++t) {
+    for (int t = 0; t < kFirstRestTile; ++t) {
         const int ni = kG1Tiles[t].ni, wm = kG1Tiles[t].wm;
         if (ni * wm > (f32 ? 5 : 7)) continue;  // larger accumulator sets leave one wave per SIMD
         const double padded = (double)(cdiv(ncol, 16 * ni) * 16 * ni);
@@ -485,34 +486,30 @@ int pick_g1_tile(int64_t ncol, bool f32 = false) {
     return best;
 }
 
-// Default for the single build: one tile, or (FP64) the first columns with the
-// (7,1) tile and the remainder with the narrowest one-wave-row tile that
-// covers it, when that pads fewer columns (nocc=200: 112 + 96 = 208 columns
-// computed instead of 224).
+// Default for the single build: one tile, or the default tile over the
+// first columns (a whole number of its widths) and the narrowest tile with
+// one wavefront row (WM = 1) over the rest, when that pads fewer columns
+// (nocc=200: FP64 112 + 96 = 208 columns computed instead of 224; FP32
+// 160 + 48 = 208 instead of 240).
 struct G1Split {
     int t0, t1;
     int64_t n0;  // columns [0, n0) with tile t0, [n0, ncol) with t1
 };
-inline int g1_tile_index(int ni, int wm) {
-    for (int t = 0; t < kNumG1Tiles; ++t)
-        if (kG1Tiles[t].ni == ni && kG1Tiles[t].wm == wm) return t;
-    return -1;
-}
 G1Split pick_g1_split(int64_t ncol, bool f32) {
     const int single = pick_g1_tile(ncol, f32);
     G1Split sp{single, single, ncol};
-    if (f32) return sp;
     const int64_t w = 16 * kG1Tiles[single].ni;
+    if (kG1Tiles[single].wm != 1) return sp;
     const int64_t padded_single = cdiv(ncol, w) * w;
-    const int t7 = g1_tile_index(7, 1);
-    const int64_t n0 = (ncol / 112) * 112, rest = ncol - n0;
-    if (t7 < 0 || n0 == 0 || rest == 0) return sp;
-    for (int ni : {5, 6, 7}) {  // narrowest tile covering the rest
-        const int t = g1_tile_index(ni, 1);
-        if (t < 0 || 16 * ni < rest) continue;
-        if (n0 + 16 * ni < padded_single) sp = G1Split{t7, t, n0};
-        break;
+    const int64_t n0 = (ncol / w) * w, rest = ncol - n0;
+    if (n0 == 0 || rest == 0) return sp;
+    int best = -1;
+    for (int t = 0; t < kNumG1Tiles; ++t) {
+        const int ni = kG1Tiles[t].ni;
+        if (kG1Tiles[t].wm != 1 || 16 * ni < rest || ni > kG1Tiles[single].ni) continue;
+        if (best < 0 || ni < kG1Tiles[best].ni) best = t;
     }
+    if (best >= 0 && n0 + 16 * kG1Tiles[best].ni < padded_single) sp = G1Split{single, best, n0};
     return sp;
 }
 
@@ -625,7 +622,7 @@ typedef int (*KbLaunch)(hipStream_t, int, const MolDesc*, const PhaseList&);
 #define KBT(a, b) launch_kb_gemm1<a, b>
 const KbLaunch kKbTiles[] = {KBT(1, 2), KBT(2, 2), KBT(3, 2), KBT(4, 2), KBT(5, 2), KBT(6, 2),
                              KBT(7, 2), KBT(8, 2), KBT(13, 1), KBT(4, 4), KBT(7, 1), KBT(5, 1),
-                             KBT(6, 1)};
+                             KBT(6, 1), KBT(3, 1)};
 #undef KBT
 static_assert(sizeof(kKbTiles) / sizeof(kKbTiles[0]) == kNumG1Tiles, "tile tables differ");
 
