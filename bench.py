@@ -623,7 +623,8 @@ def main():
         "phase_ms": {"J": j_ms, "J_rho": jr_ms, "J_out": jo_ms, "K": k_ms, "K_gemm1": g1_ms,
                      "K_syrk": sy_ms, "K_finish": avg("K_finish")},
         "roofline": {
-            "kernel": "k_gemm1_f64" if args.dtype == "f64" else "k_gemm1_f32",
+            "kernel": ("k_gemm1_f64" if args.dtype == "f64" else "k_gemm1_f32") + " (GEMM1 phase; the orbital "
+                      "columns may be covered by two launches of different tiles)",
             "bound": "mfma",
             "achieved": g1_flops / g1_ms / 1e9,
             "peak": peak,
