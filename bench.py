@@ -673,6 +673,32 @@ def main():
         res["j_8_densities"] = {"ms": jm_ms, "ms_per_density": jm_ms / nd, "speedup_vs_8_single": nd * j_ms / jm_ms,
                                 "b_stream_gbs": jbytes / jm_ms / 1e6}
         del Dm, Jm
+    # K of a second-order SCF trial density D = C_vir x C_occ^T + its
+    # transpose, from the two factors (two GEMM1 passes + the full product)
+    if dt_code == pkg.DFJK_F64:
+        Cb = synth.C_occ(cfg.seed, cfg.nao, cfg.nao)
+        x = synth.rotation(cfg.seed, cfg.nao - cfg.nocc, cfg.nocc)
+        Ld = torch.from_numpy(np.ascontiguousarray(Cb[:, cfg.nocc:] @ x)).cuda()
+        Rd = torch.from_numpy(np.ascontiguousarray(Cb[:, :cfg.nocc])).cuda()
+        Kp = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+        pkg.dfjk_build_K_pair(h.h, Ld, Rd, cfg.nocc, 1, 1.0, Kp)
+        torch.cuda.synchronize()
+        pkg.dfjk_profile(h.h, max(args.steps, 1))
+        e0.record()
+        for _ in range(args.steps):
+            pkg.dfjk_build_K_pair(h.h, Ld, Rd, cfg.nocc, 1, 1.0, Kp)
+        e1.record()
+        torch.cuda.synchronize()
+        kp_ms = e0.elapsed_time(e1) / args.steps
+        pp = pkg.dfjk_profile_read(h.h)
+        pkg.dfjk_profile(h.h, 0)
+        kp_g1 = pp["K_gemm1"][0] / max(pp["K_gemm1"][1], 1)
+        kp_sy = pp["K_syrk"][0] / max(pp["K_syrk"][1], 1)
+        kp_flops = 2 * g1_flops + 2 * sy_flops  # X_L and X_R; sum_P X_L X_R^T + X_R X_L^T (lower tiles)
+        res["k_response_density"] = {
+            "ms": kp_ms, "tflops": kp_flops / kp_ms / 1e9, "gemm1_ms": kp_g1, "gemm1_tflops": 2 * g1_flops / kp_g1 / 1e9,
+            "gemm2_ms": kp_sy, "gemm2_tflops": 2 * sy_flops / kp_sy / 1e9, "ratio_to_k_occ": kp_ms / k_ms}
+        del Ld, Rd, Kp
     res["measured_mfma_ceiling_tflops"] = {
         "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
         "bf16_16x16x32": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}

@@ -218,6 +218,27 @@ int dfjk_build_K_factored(dfjk_handle h, const double* C_dev, int64_t ncol,
                           const double* sign_dev, double scale, double* K_dev);
 
 /*
+ * Exchange for a density given by two factors, D = L R^T (Sec. IV.C.2, Eq.
+ * eq:df:eri, with K_{mu nu} = sum_{ka la} (mu ka|nu la) D_{ka la}; D need not
+ * be symmetric).  Such densities are what the second-order SCF's orbital
+ * Hessian contracts (Sec. IV.B, SOSCF): for an occupied-virtual rotation x
+ * the trial density is C_vir x C_occ^T plus its transpose, i.e. L = C_vir x,
+ * R = C_occ, sym = 1, at the cost of two K(C_occ) builds instead of a full-
+ * rank factorisation of D.
+ *   L_dev, R_dev  nao x ncol FP64 device matrices, row-major (1 <= ncol <= nao).
+ *   sym = 0       K = scale * sum_P (B_P L)(B_P R)^T         (not symmetric)
+ *   sym = 1       K = scale * sum_P [(B_P L)(B_P R)^T + (B_P R)(B_P L)^T],
+ *                 exactly symmetric (K of D + D^T).
+ *   K_dev         nao x nao FP64 output, overwritten.
+ * FP64 B runs on the FP64 matrix cores; FP32, BF16 and FP16 B on the FP32
+ * matrix cores (the k16 option does not apply: its path takes one factor).
+ * Workspace: X for 2 * naux * ncol rows.  DFJK_E_INVALID for a null pointer,
+ * ncol outside [1, nao] or sym not 0/1.  Asynchronous on the handle's stream.
+ */
+int dfjk_build_K_pair(dfjk_handle h, const double* L_dev, const double* R_dev, int64_t ncol, int sym,
+                      double scale, double* K_dev);
+
+/*
  * Per-kernel timing.  dfjk_profile(h, cap) (cap > 0) makes later calls record
  * HIP events on the handle's stream around each phase, for up to cap calls
  * per phase; cap = 0 turns it off.  dfjk_profile_read waits for the stream

@@ -9,6 +9,7 @@ Contents, each following the passage it cites:
 
 * ``df_diagonal`` -- sum_P T[P, mu nu]^2 per packed pair (Sec. IV.C.2).
 * ``form_B`` -- T = L^-1 Q from the metric Cholesky factor (Sec. IV.C.2).
+* ``K_pair_rows`` -- row-sampled K of a two-factor density D = L R^T.
 * ``rho``, ``J``, ``K_C``, ``K_D``, ``K_C_rows`` -- the J/K contractions of
   Sec. IV.C.2, Eq. eq:df:eri, written as plain loops in ``oracle.c``.
 * ``energies`` -- E_J = 1/2 sum_P rho_P^2 = 1/2 tr(DJ) and E_K = -1/4 tr(DK).
@@ -147,6 +148,21 @@ def K_C_rows(Bsel: np.ndarray, C: np.ndarray) -> np.ndarray:
     if lib().oracle_K_C_rows(_dp(Bsel), nsel, nao, naux, _dp(C), C.shape[1], _dp(out)) != 0:
         raise MemoryError("oracle_K_C_rows")
     return out
+
+
+def K_pair_rows(Bsel: np.ndarray, L: np.ndarray, R: np.ndarray, sym: bool = False) -> np.ndarray:
+    """Exchange entries among a set of rows mu_r for the two-factor density
+    D = L R^T (plus R L^T when sym), from the row slices Bsel[r, P, ka] =
+    B_P[mu_r, ka]: K[mu_r, mu_s] = sum_P sum_i (B_P L)[mu_r, i] (B_P R)[mu_s, i],
+    i.e. sum_P (B_P D B_P) restricted to those rows (Sec. IV.C.2)."""
+    Bsel = _f64(Bsel)
+    XL = Bsel @ _f64(L)  # (nsel, naux, ncol)
+    XR = Bsel @ _f64(R)
+    nsel = Bsel.shape[0]
+    out = np.zeros((nsel, nsel))
+    for P in range(Bsel.shape[1]):  # plain sum over the auxiliary index
+        out += XL[:, P, :] @ XR[:, P, :].T
+    return out + out.T if sym else out
 
 
 def form_B(M: np.ndarray, Q: np.ndarray) -> np.ndarray:

@@ -193,6 +193,25 @@ int dfjk_build_K_factored(dfjk_handle h, const double* C_dev, int64_t ncol, cons
     return k_build_factored(h, C_dev, ncol, sign_dev, scale, K_dev);
 }
 
+int dfjk_build_K_pair(dfjk_handle h, const double* L_dev, const double* R_dev, int64_t ncol, int sym,
+                      double scale, double* K_dev) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!L_dev || !R_dev || !K_dev) {
+        set_error("dfjk_build_K_pair: null L, R or K");
+        return DFJK_E_INVALID;
+    }
+    if (ncol < 1 || ncol > h->nao) {
+        set_error("dfjk_build_K_pair: ncol=%lld outside [1, nao=%lld]", (long long)ncol, (long long)h->nao);
+        return DFJK_E_INVALID;
+    }
+    if (sym != 0 && sym != 1) {
+        set_error("dfjk_build_K_pair: sym=%d is neither 0 nor 1", sym);
+        return DFJK_E_INVALID;
+    }
+    return k_build_pair(h, L_dev, R_dev, ncol, sym, scale, K_dev);
+}
+
 int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const double* D_dev,
                  double* K_dev) {
     clear_error();

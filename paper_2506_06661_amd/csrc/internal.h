@@ -111,6 +111,8 @@ int j_out_count();
 // K launchers (k_kernels.hip)
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,
                      double* K);
+int k_build_pair(dfjk_ctx* h, const double* L, const double* R, int64_t ncol, int sym, double scale,
+                 double* K);
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K);
 int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K);
 int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, int flags,

@@ -281,29 +281,43 @@ struct SyStage {
     T a[8], b[8];
 };
 
-template <typename T>
+// GEMM2 modes.  SY_SYM: K = sum_k s_k x_k x_k^T over the rows of one X,
+// lower tiles.  For two factors (D = L R^T) X holds X_L (rows 0..n) and then
+// X_R (rows n..2n), and row k of the second operand is row (k + n) mod 2n:
+// SY_PAIR_FULL contracts k < n over all tiles (sum_k xL_k xR_k^T);
+// SY_PAIR_LOWER contracts k < 2n over the lower tiles, which adds the
+// transpose (sum_k xL_k xR_k^T + xR_k xL_k^T, a symmetric result).
+enum { SY_SYM = 0, SY_PAIR_LOWER = 1, SY_PAIR_FULL = 2 };
+
+template <typename T, int MODE>
 __device__ inline void sy_load(SyStage<T>& st, const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                int64_t nao, int64_t ncol, const double* __restrict__ sign, int64_t k0,
-                               int64_t kend, int64_t mu0, int64_t nu0, int tid) {
+                               int64_t kend, int64_t mu0, int64_t nu0, int64_t boff, int tid) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int k = tid / SY_T + 2 * j, m = tid % SY_T;
         const int64_t row = k0 + k;
         const bool ok = row < kend;
         const T* xr = X + row * ldx;
+        const T* xb = xr;
+        if constexpr (MODE != SY_SYM) {
+            const int64_t rb = row + boff;
+            xb = X + (rb >= 2 * boff ? rb - 2 * boff : rb) * ldx;
+        }
         st.a[j] = (ok && mu0 + m < nao) ? xr[mu0 + m] : T(0);
-        T bv = (ok && nu0 + m < nao) ? xr[nu0 + m] : T(0);
+        T bv = (ok && nu0 + m < nao) ? xb[nu0 + m] : T(0);
         if (sign && ok && sign[row % ncol] < 0) bv = -bv;
         st.b[j] = bv;
     }
 }
 
-// partial[(s*ntl + t)][m][n] = sum_{k in split s} X[k][mu0+m] * sign_k * X[k][nu0+n]
-// grid: x = lower tile t (I >= J), y = split s
-template <typename T>
+// partial[(s*ntl + t)][m][n] = sum_{k in split s} X[k][mu0+m] * sign_k * X[k'][nu0+n]
+// (k' = k, or the row paired with k for two factors); block id = s*ntl + t,
+// t a lower tile (I >= J) or, for SY_PAIR_FULL, any tile (I = t / nt)
+template <typename T, int MODE = SY_SYM>
 __device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                    int64_t nao, int64_t ncol, const double* __restrict__ sign,
-                                   int64_t kchunk, int64_t ntl, T* __restrict__ part) {
+                                   int64_t kchunk, int64_t ntl, T* __restrict__ part, int64_t boff = 0) {
     // FP32 reads cover 4 rows x 16 columns over 64 banks: pitch 144 = 16 mod 64
     constexpr int PS = sizeof(T) == 4 ? SY_T + 16 : SY_T + 1;
     __shared__ T sA[2][KC][PS];
@@ -311,10 +325,17 @@ __device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t t = lid % ntl;
-    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > t) --I;
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    const int64_t J = t - I * (I + 1) / 2;
+    int64_t I, J;
+    if constexpr (MODE == SY_PAIR_FULL) {
+        const int64_t nt = cdiv(nao, SY_T);
+        I = t / nt;
+        J = t % nt;
+    } else {
+        I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > t) --I;
+        while ((I + 1) * (I + 2) / 2 <= t) ++I;
+        J = t - I * (I + 1) / 2;
+    }
     const int64_t mu0 = I * SY_T, nu0 = J * SY_T;
     const int64_t s = lid / ntl;
     const int64_t kbeg = s * kchunk;
@@ -329,7 +350,7 @@ __device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t
     if (kbeg < kend) {
         const int64_t nchunks = cdiv(kend - kbeg, KC);
         SyStage<T> st;
-        sy_load(st, X, ldx, nrows, nao, ncol, sign, kbeg, kend, mu0, nu0, tid);
+        sy_load<T, MODE>(st, X, ldx, nrows, nao, ncol, sign, kbeg, kend, mu0, nu0, boff, tid);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             sA[0][tid / SY_T + 2 * j][tid % SY_T] = st.a[j];
@@ -339,7 +360,9 @@ __device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int buf = ch & 1;
             const bool more = ch + 1 < nchunks;
-            if (more) sy_load(st, X, ldx, nrows, nao, ncol, sign, kbeg + (ch + 1) * KC, kend, mu0, nu0, tid);
+            if (more)
+                sy_load<T, MODE>(st, X, ldx, nrows, nao, ncol, sign, kbeg + (ch + 1) * KC, kend, mu0, nu0, boff,
+                                 tid);
 #pragma unroll
             for (int kk = 0; kk < KC / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
@@ -377,13 +400,15 @@ __device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t
             }
 }
 
-template <typename T>
+template <typename T, int MODE = SY_SYM>
 __global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                                     int64_t nao, int64_t ncol,
                                                     const double* __restrict__ sign, int64_t kchunk,
-                                                    int64_t ntl, int64_t nblk, T* __restrict__ part) {
+                                                    int64_t ntl, int64_t nblk, T* __restrict__ part,
+                                                    int64_t boff) {
     // all tiles of one split run on one XCD and share its L2 copy of the X rows
-    k_syrk_body<T>(xcd_logical(blockIdx.x, nblk), X, ldx, nrows, nao, ncol, sign, kchunk, ntl, part);
+    k_syrk_body<T, MODE>(xcd_logical(blockIdx.x, nblk), X, ldx, nrows, nao, ncol, sign, kchunk, ntl, part,
+                         boff);
 }
 
 // K[mu][nu] = K[nu][mu] = scale * sum_s partial[s][t][m][n] over the lower
@@ -421,6 +446,29 @@ __global__ __launch_bounds__(kThreads) void k_syrk_finish(const T* __restrict__ 
     const int sub = (int)(blockIdx.x % kFinSub);
     k_syrk_finish_body<T>(blockIdx.x / kFinSub, sub * per, (sub + 1) * per, part, nsplit, ntl, nao, scale,
                           K);
+}
+
+// Full-tile finish (two factors, no symmetry): K[mu][nu] = scale * sum_s
+// partial[s][t][m][n] with t = I * nt + J.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pair_finish(const T* __restrict__ part, int64_t nsplit,
+                                                           int64_t nt, int64_t nao, double scale,
+                                                           double* __restrict__ K) {
+    constexpr int per = SY_T * SY_T / kFinSub;
+    const int64_t t = blockIdx.x / kFinSub;
+    const int sub = (int)(blockIdx.x % kFinSub);
+    const int64_t I = t / nt, J = t % nt;
+    const int64_t stride = nt * nt * (int64_t)(SY_T * SY_T);
+    for (int e = sub * per + (int)threadIdx.x; e < (sub + 1) * per; e += kThreads) {
+        const int m = e / SY_T, n = e % SY_T;
+        const int64_t mu = I * SY_T + m, nu = J * SY_T + n;
+        if (mu >= nao || nu >= nao) continue;
+        const T* p = part + t * (int64_t)(SY_T * SY_T) + e;
+        double v = 0.0;
+#pragma unroll 8
+        for (int64_t s = 0; s < nsplit; ++s) v += (double)p[s * stride];  // fixed order
+        K[mu * nao + nu] = v * scale;
+    }
 }
 
 template <typename T, typename TS, int NI, int WM>
@@ -513,6 +561,31 @@ G1Split pick_g1_split(int64_t ncol, bool f32) {
     return sp;
 }
 
+// X = (B_P C)^T for every P, with the handle's forced tile or the default
+// split (profiled as the GEMM1 phase).
+int run_gemm1(dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx, bool f32) {
+    if (h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles)
+        return kG1Tiles[h->g1_tile].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, ncol);
+    G1Split sp = pick_g1_split(ncol, f32);
+    int rc = kG1Tiles[sp.t0].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, sp.n0);
+    if (!rc && sp.n0 < ncol) rc = kG1Tiles[sp.t1].by_dtype[h->dtype](h, C, ncol, X, ldx, sp.n0, ncol);
+    return rc;
+}
+
+// Splits of a GEMM2 contraction of nrows terms over ntl output tiles: about
+// 2048 workgroups, and for FP32 no running sum longer than kMaxSum32 terms
+// (the split partials are added in FP64).
+void syrk_splits(int64_t nrows, int64_t ntl, bool f32, int64_t* nsplit_out, int64_t* kchunk_out) {
+    int64_t nsplit = cdiv(2048, ntl);
+    if (f32 && nsplit < cdiv(nrows, kMaxSum32)) nsplit = cdiv(nrows, kMaxSum32);
+    const int64_t max_split = cdiv(nrows, 256);
+    if (nsplit > max_split) nsplit = max_split;
+    if (nsplit < 1) nsplit = 1;
+    const int64_t kchunk = cdiv(cdiv(nrows, nsplit), KC) * KC;
+    *nsplit_out = cdiv(nrows, kchunk);
+    *kchunk_out = kchunk;
+}
+
 template <typename T>
 int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, double scale, double* K) {
     const int64_t ldx = h->nao;
@@ -523,32 +596,19 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
 
     h->prof.begin(PH_K, h->stream);
     h->prof.begin(PH_K_GEMM1, h->stream);
-    if (h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles) {
-        rc = kG1Tiles[h->g1_tile].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, ncol);
-    } else {
-        G1Split sp = pick_g1_split(ncol, sizeof(T) == 4);
-        rc = kG1Tiles[sp.t0].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, sp.n0);
-        if (!rc && sp.n0 < ncol) rc = kG1Tiles[sp.t1].by_dtype[h->dtype](h, C, ncol, X, ldx, sp.n0, ncol);
-    }
+    rc = run_gemm1(h, C, ncol, X, ldx, sizeof(T) == 4);
     h->prof.end(PH_K_GEMM1, h->stream);
     if (rc) return rc;
 
     const int64_t nt = cdiv(h->nao, SY_T);
     const int64_t ntl = nt * (nt + 1) / 2;
-    // about 2048 workgroups, and for FP32 no running sum longer than
-    // kMaxSum32 terms (the split partials are added in FP64)
-    int64_t nsplit = cdiv(2048, ntl);
-    if (sizeof(T) == 4 && nsplit < cdiv(nrows, kMaxSum32)) nsplit = cdiv(nrows, kMaxSum32);
-    const int64_t max_split = cdiv(nrows, 256);
-    if (nsplit > max_split) nsplit = max_split;
-    if (nsplit < 1) nsplit = 1;
-    int64_t kchunk = cdiv(cdiv(nrows, nsplit), KC) * KC;
-    nsplit = cdiv(nrows, kchunk);
+    int64_t nsplit, kchunk;
+    syrk_splits(nrows, ntl, sizeof(T) == 4, &nsplit, &kchunk);
     if ((rc = h->kpart.ensure(sizeof(T) * (size_t)(nsplit * ntl) * SY_T * SY_T))) return rc;
     T* part = static_cast<T*>(h->kpart.ptr);
     h->prof.begin(PH_K_SYRK, h->stream);
     k_syrk<T><<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
-        X, ldx, nrows, h->nao, ncol, sign, kchunk, ntl, ntl * nsplit, part);
+        X, ldx, nrows, h->nao, ncol, sign, kchunk, ntl, ntl * nsplit, part, 0);
     h->prof.end(PH_K_SYRK, h->stream);
     DFJK_LAUNCH_CHECK("k_syrk");
     h->prof.begin(PH_K_FINISH, h->stream);
@@ -557,6 +617,55 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
     h->prof.end(PH_K_FINISH, h->stream);
     h->prof.end(PH_K, h->stream);
     DFJK_LAUNCH_CHECK("k_syrk_finish");
+    return DFJK_OK;
+}
+
+// Two factors, D = L R^T (L, R: nao x ncol): X_L = (B_P L)^T and X_R =
+// (B_P R)^T are stored one after the other, then
+//   sym = 0: K = scale * sum_P X_L^T X_R            (all output tiles)
+//   sym = 1: K = scale * sum_P (X_L^T X_R + X_R^T X_L)  (lower tiles, mirrored)
+template <typename T>
+int k_build_pair_t(dfjk_ctx* h, const void* L, const void* R, int64_t ncol, int sym, double scale, double* K) {
+    const int64_t ldx = h->nao;
+    const int64_t n1 = h->naux * ncol;  // rows of X_L (and of X_R)
+    int rc;
+    if ((rc = h->X.ensure(sizeof(T) * (size_t)(2 * n1) * (size_t)ldx))) return rc;
+    T* X = static_cast<T*>(h->X.ptr);
+
+    h->prof.begin(PH_K, h->stream);
+    h->prof.begin(PH_K_GEMM1, h->stream);
+    rc = run_gemm1(h, L, ncol, X, ldx, sizeof(T) == 4);
+    if (!rc) rc = run_gemm1(h, R, ncol, X + n1 * ldx, ldx, sizeof(T) == 4);
+    h->prof.end(PH_K_GEMM1, h->stream);
+    if (rc) return rc;
+
+    const int64_t nt = cdiv(h->nao, SY_T);
+    const int64_t ntl = sym ? nt * (nt + 1) / 2 : nt * nt;
+    const int64_t nrows = sym ? 2 * n1 : n1;  // contraction length
+    int64_t nsplit, kchunk;
+    syrk_splits(nrows, ntl, sizeof(T) == 4, &nsplit, &kchunk);
+    if ((rc = h->kpart.ensure(sizeof(T) * (size_t)(nsplit * ntl) * SY_T * SY_T))) return rc;
+    T* part = static_cast<T*>(h->kpart.ptr);
+    const dim3 grid((unsigned)(ntl * nsplit));
+    h->prof.begin(PH_K_SYRK, h->stream);
+    if (sym)
+        k_syrk<T, SY_PAIR_LOWER><<<grid, kThreads, 0, h->stream>>>(X, ldx, nrows, h->nao, ncol, nullptr, kchunk,
+                                                                     ntl, ntl * nsplit, part, n1);
+    else
+        k_syrk<T, SY_PAIR_FULL><<<grid, kThreads, 0, h->stream>>>(X, ldx, nrows, h->nao, ncol, nullptr, kchunk,
+                                                                    ntl, ntl * nsplit, part, n1);
+    h->prof.end(PH_K_SYRK, h->stream);
+    DFJK_LAUNCH_CHECK("k_syrk (two factors)");
+    h->prof.begin(PH_K_FINISH, h->stream);
+    if (sym)
+        k_syrk_finish<T><<<dim3((unsigned)(ntl * kFinSub)), kThreads, 0, h->stream>>>(part, nsplit, ntl,
+                                                                                       h->nao, scale, K);
+    else
+        k_pair_finish<T><<<dim3((unsigned)(ntl * kFinSub)), kThreads, 0, h->stream>>>(part, nsplit, nt, h->nao,
+                                                                                       scale, K);
+    h->prof.end(PH_K_FINISH, h->stream);
+    h->prof.end(PH_K, h->stream);
+    DFJK_LAUNCH_CHECK("k finish (two factors)");
     return DFJK_OK;
 }
 
@@ -667,6 +776,21 @@ int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* s
         DFJK_LAUNCH_CHECK("to_f32");
         return k_build_t<float>(h, Cf, ncol, sign, scale, K);
     }
+}
+
+int k_build_pair(dfjk_ctx* h, const double* L, const double* R, int64_t ncol, int sym, double scale, double* K) {
+    if (h->dtype == DFJK_F64) return k_build_pair_t<double>(h, L, R, ncol, sym, scale, K);
+    // FP32 compute for FP32, BF16 and FP16 storage of B (also with the k16
+    // option: the 16-bit exchange takes one factor)
+    int rc;
+    const int64_t n = h->nao * ncol;
+    if ((rc = h->Cw.ensure(sizeof(float) * (size_t)(2 * n)))) return rc;
+    float* Lf = static_cast<float*>(h->Cw.ptr);
+    float* Rf = Lf + n;
+    to_f32<<<dim3((unsigned)cdiv(n, 256)), 256, 0, h->stream>>>(L, n, Lf);
+    to_f32<<<dim3((unsigned)cdiv(n, 256)), 256, 0, h->stream>>>(R, n, Rf);
+    DFJK_LAUNCH_CHECK("to_f32");
+    return k_build_pair_t<float>(h, Lf, Rf, ncol, sym, scale, K);
 }
 
 

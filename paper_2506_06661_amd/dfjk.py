@@ -68,6 +68,7 @@ def lib():
         L.dfjk_form_B.argtypes = [i64, i64, vp, vp, i64, vp]
         L.dfjk_build_K.argtypes = [vp, vp, i64, vp, vp]
         L.dfjk_build_K_factored.argtypes = [vp, vp, i64, vp, dbl, vp]
+        L.dfjk_build_K_pair.argtypes = [vp, vp, vp, i64, i32, dbl, vp]
         L.dfjk_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.dfjk_destroy.argtypes = [vp]
         L.dfjk_destroy.restype = None
@@ -115,7 +116,7 @@ def lib():
         L.dfjk_set_tile.argtypes = [vp, i32, i32]
         L.dfjk_profile.argtypes = [vp, i32]
         L.dfjk_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32), i32]
-        for name in ("dfjk_scf_step", "dfjk_scf_reset", "dfjk_tile_count", "dfjk_tile_info", "dfjk_set_tile", "dfjk_profile", "dfjk_profile_read", "dfjk_init", "dfjk_build_J", "dfjk_build_K", "dfjk_build_K_factored",
+        for name in ("dfjk_scf_step", "dfjk_scf_reset", "dfjk_tile_count", "dfjk_tile_info", "dfjk_set_tile", "dfjk_profile", "dfjk_profile_read", "dfjk_init", "dfjk_build_J", "dfjk_build_K", "dfjk_build_K_factored", "dfjk_build_K_pair",
                      "dfjk_workspace_bytes", "dfjk_quantize"):
             getattr(L, name).restype = i32
         _lib = L
@@ -187,6 +188,11 @@ def dfjk_build_K(h, Cocc, nocc: int, D, K) -> int:
 def dfjk_build_K_factored(h, C, ncol: int, sign, scale: float, K) -> int:
     return _check("dfjk_build_K_factored",
                   lib().dfjk_build_K_factored(h, _ptr(C), ncol, _ptr(sign), scale, _ptr(K)))
+
+
+def dfjk_build_K_pair(h, L, R, ncol: int, sym: int, scale: float, K) -> int:
+    return _check("dfjk_build_K_pair",
+                  lib().dfjk_build_K_pair(h, _ptr(L), _ptr(R), ncol, sym, scale, _ptr(K)))
 
 
 def dfjk_workspace_bytes(h) -> int:
@@ -413,6 +419,12 @@ class Handle:
         dev = (C if C is not None else D).device
         K = torch.empty((self.nao, self.nao), dtype=torch.float64, device=dev)
         dfjk_build_K(self.h, C, 0 if C is None else C.shape[1], D, K)
+        return K
+
+    def K_pair(self, L: torch.Tensor, R: torch.Tensor, sym: bool = False, scale: float = 1.0) -> torch.Tensor:
+        """K of the density D = L R^T (plus its transpose when sym)."""
+        K = torch.empty((self.nao, self.nao), dtype=torch.float64, device=L.device)
+        dfjk_build_K_pair(self.h, L, R, L.shape[1], int(sym), scale, K)
         return K
 
     def workspace_bytes(self) -> int:

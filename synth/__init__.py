@@ -45,6 +45,7 @@ STREAM_JITTER = 6
 STREAM_BATCH = 7
 STREAM_MLP = 8
 STREAM_METRIC = 9
+STREAM_ROT = 10
 
 
 def build() -> str:
@@ -210,6 +211,12 @@ def C_occ(seed: int, nao: int, nocc: int) -> np.ndarray:
     G = normal(seed, STREAM_COCC, nao * nocc).reshape(nao, nocc)
     Q, _ = np.linalg.qr(G)
     return np.ascontiguousarray(Q)
+
+
+def rotation(seed: int, nvir: int, nocc: int, amp: float = 0.1) -> np.ndarray:
+    """Occupied-virtual rotation amplitudes x (nvir x nocc), amp * N(0,1):
+    the trial vectors of a second-order SCF step."""
+    return np.ascontiguousarray(amp * normal(seed, STREAM_ROT, nvir * nocc).reshape(nvir, nocc))
 
 
 def core_hamiltonian(seed: int, R: np.ndarray) -> np.ndarray:

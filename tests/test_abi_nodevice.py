@@ -48,6 +48,7 @@ def test_invalid_arguments(L):
     assert L.dfjk_form_B(4, 5, fake, fake, 4, None) == -1  # ldQ < ncol
     assert L.dfjk_build_K(None, fake, 3, None, fake) == -1
     assert L.dfjk_build_K_factored(None, fake, 3, None, ctypes.c_double(1.0), fake) == -1
+    assert L.dfjk_build_K_pair(None, fake, fake, 3, 0, ctypes.c_double(1.0), fake) == -1
     n = ctypes.c_size_t()
     assert L.dfjk_workspace_bytes(None, ctypes.byref(n)) == -1
     L.dfjk_destroy(None)  # no-op

@@ -6,6 +6,8 @@ benchmark times (default tiles, options and split factors).
   row-sampled exchange, which needs only the packed columns of those rows;
   the Coulomb energy E_J = 1/2 sum_P rho_P^2.  Tolerance 1e-10 relative to
   the largest reference entry.
+* The same workload, K of a two-factor density D = L R^T (with and without
+  its transpose) on the same 12 rows, 1e-10.
 * The same workload with B stored in FP32 (one rounding from FP64): rho and
   J in full against the oracle on the rounded B (FP64 accumulation: 1e-10);
   K rows against the oracle on the rounded B within a probabilistic bound for
@@ -169,6 +171,28 @@ def test_c2_fp32_full(pkg, c2):
     err_i = float(np.abs(K[np.ix_(rows, rows)] - K_i).max() / np.abs(K_i).max())
     print(f"C2 FP32 B: rho {max_rel(rho, rho_o):.1e} J {max_rel(J, J_o):.1e} K rows (ii) {err_k:.1e} "
           f"(i) {err_i:.1e}")
+
+
+def test_c2_pair_K(pkg, c2):
+    """K of a second-order SCF trial density D = C_vir x C_occ^T (+ D^T) from
+    its two factors at nao=1024, naux=4096, nocc=200, FP64 B, sampled rows."""
+    cfg, R, B, _, _ = c2
+    Cb = synth.C_occ(cfg.seed, cfg.nao, cfg.nao)
+    x = synth.rotation(cfg.seed, cfg.nao - cfg.nocc, cfg.nocc)
+    L, Rm = np.ascontiguousarray(Cb[:, cfg.nocc:] @ x), np.ascontiguousarray(Cb[:, :cfg.nocc])
+    h = pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao)
+    Ld, Rd = torch.from_numpy(L).cuda(), torch.from_numpy(Rm).cuda()
+    rows = sample_rows(cfg.nao)
+    Bsel = row_slices(cfg, R, rows)
+    for sym in (0, 1):
+        print(f"case pair K sym={sym}", flush=True)
+        K = host(h.K_pair(Ld, Rd, sym=bool(sym)))
+        K_o = oracle.K_pair_rows(Bsel, L, Rm, sym=bool(sym))
+        err = float(np.abs(K[np.ix_(rows, rows)] - K_o).max() / np.abs(K_o).max())
+        assert err < 1e-10, err
+        if sym:
+            assert np.array_equal(K, K.T)
+    h.close()
 
 
 def test_c2_form_B(pkg, c2):

@@ -224,6 +224,30 @@ def test_selected_rows(c1):
     assert np.abs(Ksel - Km[np.ix_(rows, rows)]).max() < 1e-12 * np.abs(Km).max()
 
 
+def test_pair_rows_bruteforce(c1):
+    """Row-sampled K of D = L R^T (a second-order SCF trial density, L =
+    C_vir x, R = C_occ) equals the four-index contraction sum (mu ka|nu la)
+    D[ka, la] on those rows; sym adds the transpose (K of D + D^T)."""
+    cfg, B, _, _ = c1
+    nao, nocc = cfg.nao, cfg.nocc
+    Cb = synth.C_occ(cfg.seed, nao, nao)
+    x = synth.rotation(cfg.seed, nao - nocc, nocc)
+    L, Rm = Cb[:, nocc:] @ x, Cb[:, :nocc]
+    Bm = unpack_np(B, nao).reshape(cfg.naux, nao * nao)
+    eri = (Bm.T @ Bm).reshape(nao, nao, nao, nao)
+    D = L @ Rm.T
+    K_bf = np.einsum("mknl,kl->mn", eri, D)
+    R = synth.positions(cfg)
+    rows = np.array([0, 5, 17, 40, 63])
+    Bsel = np.stack([synth.B_cols(cfg.seed, R, cfg.naux, synth.pair_index(mu, np.arange(nao)))
+                     for mu in rows])
+    sub = np.ix_(rows, rows)
+    assert np.abs(oracle.K_pair_rows(Bsel, L, Rm) - K_bf[sub]).max() < 1e-12 * np.abs(K_bf).max()
+    K_sym = np.einsum("mknl,kl->mn", eri, D + D.T)
+    assert np.abs(oracle.K_pair_rows(Bsel, L, Rm, sym=True) - K_sym[sub]).max() < 1e-12 * np.abs(K_sym).max()
+    assert not np.allclose(K_bf, K_bf.T)  # the unsymmetrised K is genuinely not symmetric
+
+
 # ----------------------------------------------------------- reduced formats
 def _all_finite(bits_to_f64):
     vals = bits_to_f64(np.arange(65536, dtype=np.uint32))
