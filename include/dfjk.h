@@ -257,11 +257,12 @@ int dfjk_profile_read(dfjk_handle h, double* total_ms, int* counts, int nphase);
  * DFJK_TILE_J_OUT selects the FP64 J pass-2 column width: (p0, p1) =
  * (packed columns per workgroup, 0).  DFJK_TILE_K16 selects the 16-bit
  * exchange's GEMM1 tile: (p0, p1) = (occupied orbitals, basis functions) per
- * workgroup.  dfjk_tile_count returns the number of
+ * workgroup.  DFJK_TILE_K16_SYRK selects the 16-bit exchange's GEMM2 output
+ * tile: p0 = p1 = its edge (128 or 256).  dfjk_tile_count returns the number of
  * compiled tiles; dfjk_set_tile makes the handle use tile `index` (-1 =
  * default).  Every tile computes the same result up to summation order.
  */
-enum { DFJK_TILE_GEMM1 = 0, DFJK_TILE_J_OUT = 1, DFJK_TILE_K16 = 2 };
+enum { DFJK_TILE_GEMM1 = 0, DFJK_TILE_J_OUT = 1, DFJK_TILE_K16 = 2, DFJK_TILE_K16_SYRK = 3 };
 int dfjk_tile_count(int kernel);
 int dfjk_tile_info(int kernel, int index, int* p0, int* p1);
 int dfjk_set_tile(dfjk_handle h, int kernel, int index);

@@ -276,14 +276,16 @@ int dfjk_tile_count(int kernel) {
     if (kernel == DFJK_TILE_GEMM1) return k_tile_count();
     if (kernel == DFJK_TILE_J_OUT) return j_out_count();
     if (kernel == DFJK_TILE_K16) return k16_tile_count();
+    if (kernel == DFJK_TILE_K16_SYRK) return k16_syrk_tile_count();
     set_error("dfjk_tile_count: unknown kernel %d", kernel);
     return DFJK_E_INVALID;
 }
 
 int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
     clear_error();
-    if ((kernel != DFJK_TILE_GEMM1 && kernel != DFJK_TILE_J_OUT && kernel != DFJK_TILE_K16) || !p0 ||
-        !p1) {
+    if ((kernel != DFJK_TILE_GEMM1 && kernel != DFJK_TILE_J_OUT && kernel != DFJK_TILE_K16 &&
+         kernel != DFJK_TILE_K16_SYRK) ||
+        !p0 || !p1) {
         set_error("dfjk_tile_info: unknown kernel or null output");
         return DFJK_E_INVALID;
     }
@@ -292,6 +294,14 @@ int dfjk_tile_info(int kernel, int index, int* p0, int* p1) {
             set_error("dfjk_tile_info: index %d out of range", index);
             return DFJK_E_INVALID;
         }
+        return DFJK_OK;
+    }
+    if (kernel == DFJK_TILE_K16_SYRK) {
+        if (index < 0 || index >= k16_syrk_tile_count()) {
+            set_error("dfjk_tile_info: index %d out of range", index);
+            return DFJK_E_INVALID;
+        }
+        *p0 = *p1 = k16_syrk_tile_size(index);
         return DFJK_OK;
     }
     if (kernel == DFJK_TILE_J_OUT) {
@@ -316,7 +326,8 @@ int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
     if (int rc = check_handle(h)) return rc;
     const int count = kernel == DFJK_TILE_GEMM1 ? k_tile_count()
                       : kernel == DFJK_TILE_J_OUT ? j_out_count()
-                      : kernel == DFJK_TILE_K16 ? k16_tile_count() : 0;
+                      : kernel == DFJK_TILE_K16 ? k16_tile_count()
+                      : kernel == DFJK_TILE_K16_SYRK ? k16_syrk_tile_count() : 0;
     if (count == 0 || index < -1 || index >= count) {
         set_error("dfjk_set_tile: kernel %d / index %d invalid", kernel, index);
         return DFJK_E_INVALID;
@@ -325,8 +336,10 @@ int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
         h->g1_tile = index;
     else if (kernel == DFJK_TILE_J_OUT)
         h->jout_tile = index;
-    else
+    else if (kernel == DFJK_TILE_K16)
         h->k16_tile = index;
+    else
+        h->k16_syrk_tile = index;
     return DFJK_OK;
 }
 

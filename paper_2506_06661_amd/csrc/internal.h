@@ -90,6 +90,7 @@ struct dfjk_ctx {
     int g1_tile = -1;       // GEMM1 tile index (-1: heuristic)
     int jout_tile = -1;     // J pass-2 column width index (-1: default)
     int k16_tile = -1;      // 16-bit GEMM1 column tile index (-1: default)
+    int k16_syrk_tile = -1; // 16-bit SYRK output tile index (-1: default)
 
     // SCF state (scf.hip): iterations done, DIIS vectors stored
     int scf_iter = 0, scf_count = 0;
@@ -123,6 +124,8 @@ int k_tile_count();
 int k_tile_info(int t, int* ni, int* wm);
 int k16_tile_count();
 int k16_tile_info(int t, int* cols, int* rows);
+int k16_syrk_tile_count();
+int k16_syrk_tile_size(int t);
 
 // Batched builds (batch.hip drives; j_kernels.hip / k_kernels.hip launch).
 // One descriptor per molecule; all pointers are device pointers.

@@ -444,25 +444,127 @@ __global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t n
             }
 }
 
-// K = scale * sum_s part[s][t] over the lower triangle, mirrored (diagonal
-// tiles use m >= n only, so K is exactly symmetric).
-// grid: kFin16 blocks per lower tile, each adding up a contiguous slice of it
-__global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ part, int64_t nsplit,
-                                                     int64_t ntl, int64_t nao, double scale,
-                                                     double* __restrict__ K) {
-    constexpr int per = 128 * 128 / kFin16;
-    const int64_t t = blockIdx.x / kFin16;
-    const int sub = (int)(blockIdx.x % kFin16);
+// Lower tile (I >= J) of 256 x 256 of K; 2 x 2 waves of 128 x 128 (64
+// accumulator blocks per wave, held in the matrix-core registers): per
+// 32-wide step each wave reads 16 operand fragments from LDS for 64
+// matrix-core steps, half the LDS and L2 traffic per step of the 128 tile.
+struct S16WStage {
+    u4 a[4], b[4];  // 256 rows x 4 pieces per operand = 1024 pieces / 256 threads
+};
+
+template <typename H>
+__global__ __launch_bounds__(kT, 1) void syrk_16w(const H* __restrict__ X, int64_t nao, int64_t ncp,
+                                                   int64_t naux, int64_t pchunk, int64_t ntl, int64_t nblk,
+                                                   float* __restrict__ part) {
+    __shared__ H sA[2][256][LROW];
+    __shared__ H sB[2][256][LROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t lid = xcd_lid(blockIdx.x, nblk);
+    const int64_t t = lid % ntl, s = lid / ntl;
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int64_t J = t - I * (I + 1) / 2;
-    const int64_t stride = ntl * (int64_t)(128 * 128);
+    const int64_t mu0 = I * 256, nu0 = J * 256;
+    const int64_t P0 = s * pchunk, P1 = P0 + pchunk < naux ? P0 + pchunk : naux;
+    v4f acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    // rows past nao read row nao-1: they only feed output rows and columns
+    // past nao, which the finish discards
+    int64_t roff_a[4], roff_b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t r = (tid >> 2) + 64 * j;
+        roff_a[j] = (mu0 + r < nao ? mu0 + r : nao - 1) * ncp + 8 * (tid & 3);
+        roff_b[j] = (nu0 + r < nao ? nu0 + r : nao - 1) * ncp + 8 * (tid & 3);
+    }
+    const int64_t nks = ncp / KS;
+    const int64_t nsteps = (P1 > P0 ? P1 - P0 : 0) * nks;  // (P, 32-wide step) in order
+    if (nsteps > 0) {
+        S16WStage st;
+        const H* Pb = X + P0 * nao * ncp;
+        int64_t kk = 0;
+        auto load = [&]() {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                st.a[j] = *reinterpret_cast<const u4*>(Pb + kk + roff_a[j]);
+                st.b[j] = *reinterpret_cast<const u4*>(Pb + kk + roff_b[j]);
+            }
+            kk += KS;
+            if (kk == ncp) {
+                kk = 0;
+                Pb += nao * ncp;
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = (tid >> 2) + 64 * j, q = tid & 3;
+                *reinterpret_cast<u4*>(&sA[buf][r][swz4(r, q)]) = st.a[j];
+                *reinterpret_cast<u4*>(&sB[buf][r][swz4(r, q)]) = st.b[j];
+            }
+        };
+        load();
+        store(0);
+        __syncthreads();
+        for (int64_t step = 0; step < nsteps; ++step) {
+            const int buf = step & 1;
+            const bool more = step + 1 < nsteps;
+            if (more) load();
+            u4 a[8], b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int ra = wm * 128 + q * 16 + (lane & 15), rb = wn * 128 + q * 16 + (lane & 15);
+                a[q] = *reinterpret_cast<const u4*>(&sA[buf][ra][swz4(ra, lane >> 4)]);
+                b[q] = *reinterpret_cast<const u4*>(&sB[buf][rb][swz4(rb, lane >> 4)]);
+            }
+#pragma unroll
+            for (int ti = 0; ti < 8; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 8; ++tj) acc[ti][tj] = Mma16<H>::step(a[ti], b[tj], acc[ti][tj]);
+            if (more) store(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    float* out = part + (s * ntl + t) * (int64_t)(256 * 256);
+#pragma unroll
+    for (int ti = 0; ti < 8; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 8; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = wm * 128 + ti * 16 + 4 * (lane >> 4) + r;
+                const int n = wn * 128 + tj * 16 + (lane & 15);
+                out[m * 256 + n] = acc[ti][tj][r];
+            }
+}
+
+// K = scale * sum_s part[s][t] over the lower triangle, mirrored (diagonal
+// tiles use m >= n only, so K is exactly symmetric).
+// grid: kFin16 blocks per lower tile, each adding up a contiguous slice of it
+// (kFin16 workgroups per 128 x 128 block of the tile)
+template <int TS>
+__global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ part, int64_t nsplit,
+                                                     int64_t ntl, int64_t nao, double scale,
+                                                     double* __restrict__ K) {
+    constexpr int nsub = kFin16 * (TS / 128) * (TS / 128);
+    constexpr int per = TS * TS / nsub;
+    const int64_t t = blockIdx.x / nsub;
+    const int sub = (int)(blockIdx.x % nsub);
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int64_t J = t - I * (I + 1) / 2;
+    const int64_t stride = ntl * (int64_t)(TS * TS);
     for (int e = sub * per + (int)threadIdx.x; e < (sub + 1) * per; e += kT) {
-        const int m = e / 128, n = e % 128;
-        const int64_t mu = I * 128 + m, nu = J * 128 + n;
+        const int m = e / TS, n = e % TS;
+        const int64_t mu = I * TS + m, nu = J * TS + n;
         if (mu >= nao || nu >= nao || (I == J && m < n)) continue;
-        const float* p = part + t * (int64_t)(128 * 128) + e;
+        const float* p = part + t * (int64_t)(TS * TS) + e;
         double v = 0.0;
 #pragma unroll 8
         for (int64_t s = 0; s < nsplit; ++s) v += (double)p[s * stride];  // fixed order
@@ -534,6 +636,11 @@ void launch_g16(int t, hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, co
     }
 }
 
+// 16-bit GEMM2 output tiles (edge); the default is set after measurement.
+constexpr int kSyrk16Tiles[] = {128, 256};
+constexpr int kNumSyrk16Tiles = 2;
+inline int pick_syrk16_tile(int64_t nao) { return nao >= 512 ? 1 : 0; }
+
 template <typename H>
 int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     const hipStream_t st = h->stream;
@@ -563,7 +670,10 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     launch_g16<H>(t, st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
-    const int64_t nt = cdiv(nao, 128), ntl = nt * (nt + 1) / 2;
+    int ts = h->k16_syrk_tile;
+    if (ts < 0 || ts >= kNumSyrk16Tiles) ts = pick_syrk16_tile(nao);
+    const int64_t T = kSyrk16Tiles[ts];
+    const int64_t nt = cdiv(nao, T), ntl = nt * (nt + 1) / 2;
     // about 2048 workgroups, and no FP32 running sum longer than kMaxSum16
     // terms (the split partials are added in FP64)
     int64_t nsplit = cdiv(2048, ntl);
@@ -571,15 +681,21 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     if (nsplit > naux) nsplit = naux;
     const int64_t pchunk = cdiv(naux, nsplit);
     nsplit = cdiv(naux, pchunk);
-    if ((rc = h->kpart.ensure(sizeof(float) * (size_t)(nsplit * ntl) * 128 * 128))) return rc;
+    if ((rc = h->kpart.ensure(sizeof(float) * (size_t)(nsplit * ntl) * T * T))) return rc;
     float* part = static_cast<float*>(h->kpart.ptr);
+    const dim3 grid((unsigned)(ntl * nsplit));
     h->prof.begin(PH_K_SYRK, st);
-    syrk_16<H><<<dim3((unsigned)(ntl * nsplit)), kT, 0, st>>>(X, nao, ncp, naux, pchunk, ntl,
-                                                                ntl * nsplit, part);
+    if (T == 256)
+        syrk_16w<H><<<grid, kT, 0, st>>>(X, nao, ncp, naux, pchunk, ntl, ntl * nsplit, part);
+    else
+        syrk_16<H><<<grid, kT, 0, st>>>(X, nao, ncp, naux, pchunk, ntl, ntl * nsplit, part);
     h->prof.end(PH_K_SYRK, st);
     DFJK_LAUNCH_CHECK("syrk_16");
     h->prof.begin(PH_K_FINISH, st);
-    syrk16_finish<<<dim3((unsigned)(ntl * kFin16)), kT, 0, st>>>(part, nsplit, ntl, nao, scale, K);
+    if (T == 256)
+        syrk16_finish<256><<<dim3((unsigned)(ntl * kFin16 * 4)), kT, 0, st>>>(part, nsplit, ntl, nao, scale, K);
+    else
+        syrk16_finish<128><<<dim3((unsigned)(ntl * kFin16)), kT, 0, st>>>(part, nsplit, ntl, nao, scale, K);
     h->prof.end(PH_K_FINISH, st);
     h->prof.end(PH_K, st);
     DFJK_LAUNCH_CHECK("syrk16_finish");
@@ -596,6 +712,10 @@ int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double*
 }
 
 int k16_tile_count() { return kNumG16Tiles; }
+
+int k16_syrk_tile_count() { return kNumSyrk16Tiles; }
+
+int k16_syrk_tile_size(int t) { return t >= 0 && t < kNumSyrk16Tiles ? kSyrk16Tiles[t] : 0; }
 
 int k16_tile_info(int index, int* cols, int* rows) {
     if (index < 0 || index >= kNumG16Tiles) return DFJK_E_INVALID;

@@ -204,6 +204,7 @@ def dfjk_workspace_bytes(h) -> int:
 DFJK_TILE_GEMM1 = 0
 DFJK_TILE_J_OUT = 1
 DFJK_TILE_K16 = 2
+DFJK_TILE_K16_SYRK = 3
 
 
 def dfjk_scf_step(h, H, D, Cocc, nocc: int, flags: int = 0, want_info: bool = True):

@@ -123,6 +123,12 @@ def test_k16_exchange(pkg, dtype, bound, nao, naux, nocc, seed):
     for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_K16)):  # every GEMM1 tile
         pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_K16, t)
         assert max_rel(host(h.K(C=dev(C))), K_ref) < bound, t
+    pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_K16, -1)
+    for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_K16_SYRK)):  # every GEMM2 tile (128, 256)
+        pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_K16_SYRK, t)
+        Kt = host(h.K(C=dev(C)))
+        assert max_rel(Kt, K_ref) < bound, t
+        assert np.array_equal(Kt, Kt.T)
 
 
 @pytest.mark.parametrize("dtype", [F32, BF16, F16])
