@@ -702,6 +702,9 @@ def main():
     res["measured_mfma_ceiling_tflops"] = {
         "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
         "bf16_16x16x32": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}
+    hbm_read = pkg.dfjk_probe_hbm_read(Bd)
+    res["measured_hbm_read_gbs"] = hbm_read
+    res["j_frac_of_measured_hbm_read"] = res["j_hbm_gbs"] / hbm_read
     res["roofline"]["frac_of_measured_ceiling"] = (
         res["roofline"]["achieved"] / res["measured_mfma_ceiling_tflops"]["f64_16x16x4" if args.dtype == "f64"
                                                                          else "f32_16x16x4"])

@@ -348,6 +348,16 @@ int dfjk_guess_assemble(const float* y_dev, const double* Dcore_dev, int64_t nao
  */
 int dfjk_probe_mfma(int dtype, double* tflops);
 
+/*
+ * Sustained HBM read rate (GB/s) of a plain streaming kernel over the first
+ * bytes (rounded down to 16) of a caller-owned device buffer, e.g. B itself:
+ * the measured ceiling of the bandwidth-bound J passes.  Contiguous ranges per
+ * workgroup at 2, 4, 8 and 16 workgroups per CU, each timed twice after one
+ * warm-up; the best rate is returned.  Waits.  DFJK_E_INVALID for a null or unaligned
+ * buffer or fewer than 16 bytes.
+ */
+int dfjk_probe_hbm_read(const void* buf_dev, size_t bytes, double* gbs);
+
 /* Device workspace currently held by the handle, in bytes. */
 int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes);
 

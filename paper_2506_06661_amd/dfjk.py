@@ -109,6 +109,8 @@ def lib():
         L.dfjk_scf_reset.argtypes = [vp]
         L.dfjk_probe_mfma.argtypes = [i32, ctypes.POINTER(dbl)]
         L.dfjk_probe_mfma.restype = i32
+        L.dfjk_probe_hbm_read.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(dbl)]
+        L.dfjk_probe_hbm_read.restype = i32
         L.dfjk_aufbau.argtypes = [vp, vp, i64, vp, vp]
         L.dfjk_aufbau.restype = i32
         L.dfjk_tile_count.argtypes = [i32]
@@ -217,6 +219,14 @@ def dfjk_scf_step(h, H, D, Cocc, nocc: int, flags: int = 0, want_info: bool = Tr
 
 def dfjk_aufbau(h, F, nocc: int, Cocc, D=None) -> int:
     return _check("dfjk_aufbau", lib().dfjk_aufbau(h, _ptr(F), nocc, _ptr(Cocc), _ptr(D)))
+
+
+def dfjk_probe_hbm_read(buf, nbytes: int | None = None) -> float:
+    """Sustained HBM read rate (GB/s) of a streaming kernel over a device tensor."""
+    out = ctypes.c_double()
+    n = buf.numel() * buf.element_size() if nbytes is None else nbytes
+    _check("dfjk_probe_hbm_read", lib().dfjk_probe_hbm_read(_ptr(buf), n, ctypes.byref(out)))
+    return out.value
 
 
 def dfjk_probe_mfma(dtype: int) -> float:

@@ -49,6 +49,10 @@ def test_invalid_arguments(L):
     assert L.dfjk_build_K(None, fake, 3, None, fake) == -1
     assert L.dfjk_build_K_factored(None, fake, 3, None, ctypes.c_double(1.0), fake) == -1
     assert L.dfjk_build_K_pair(None, fake, fake, 3, 0, ctypes.c_double(1.0), fake) == -1
+    g = ctypes.c_double()
+    L.dfjk_probe_hbm_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double)]
+    assert L.dfjk_probe_hbm_read(None, 1024, ctypes.byref(g)) == -1
+    assert L.dfjk_probe_hbm_read(ctypes.c_void_p(4097), 1024, ctypes.byref(g)) == -1  # not 16-byte aligned
     n = ctypes.c_size_t()
     assert L.dfjk_workspace_bytes(None, ctypes.byref(n)) == -1
     L.dfjk_destroy(None)  # no-op
