@@ -116,6 +116,25 @@ def test_pair_f32(pkg, sym):
     assert max_rel(K, oracle.K_D(Bq, nao, D)) < 2e-4
 
 
+def test_pair_bf16_with_k16_option(pkg):
+    """BF16 B on a handle with the k16 option: the two-factor K runs on the
+    FP32 matrix cores (the 16-bit path takes one factor), so it matches the
+    oracle on the dequantised B with L and R rounded to FP32 (2e-4)."""
+    nao, naux, nocc = 300, 40, 37
+    _, B, _ = system(nao, naux, nocc, 23)
+    L, R = factors(nao, nocc, 23)
+    Bq = oracle.quantize_bf16(B)
+    Bd = torch.empty(B.shape, dtype=torch.bfloat16, device="cuda")
+    pkg.dfjk_quantize(dev(B), Bd, 2, B.size)
+    opts = pkg.dfjk.default_options()
+    opts.k16 = 1
+    h = pkg.Handle(Bd, nao, dtype=2, opts=opts)
+    D = oracle.quantize_f32(L) @ oracle.quantize_f32(R).T
+    K = host(h.K_pair(dev(L), dev(R), sym=True))
+    assert max_rel(K, oracle.K_D(Bq, nao, D + D.T)) < 2e-4
+    assert np.array_equal(K, K.T)
+
+
 def test_pair_invalid(pkg):
     nao, naux, nocc = 64, 20, 8
     _, B, C = system(nao, naux, nocc, 21)
