@@ -232,8 +232,6 @@ def bench_c4(args):
     for name, code, _ in [("f32", pkg.DFJK_F32, None), ("bf16", pkg.DFJK_BF16, None)]:
         bt = pkg.Batch(mols[name], code)
         untuned = timed(bt.build, args.steps)
-        cache = os.path.join(ROOT, "gpurun_out", f"tiles_{name}.txt") if os.path.isdir(
-            os.path.join(ROOT, "gpurun_out")) else None
         bt.autotune(reps=3, cache_path=None)
         tiles = [bt.tile(b) for b in range(8)]
         eager = timed(bt.build, args.steps)
