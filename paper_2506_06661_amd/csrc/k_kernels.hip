@@ -573,13 +573,15 @@ int run_gemm1(dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx, bo
 }
 
 // Splits of a GEMM2 contraction of nrows terms over ntl output tiles: about
-// 8192 workgroups, and for FP32 no running sum longer than kMaxSum32 terms
-// (the split partials are added in FP64).  On MI355X at nao=1024, naux=4096,
-// nocc=200 the FP64 SYRK took 20.4 / 18.4 / 17.4 / 16.8 / 16.5 ms for about
-// 1024 / 2048 / 4096 / 8192 / 16384 workgroups, while the finish, which reads
-// every partial tile, grew from 0.07 ms (2048) to 0.24 (8192) and 0.44 (16384).
+// 8192 workgroups (FP64) or 16384 (FP32, whose partials are half the size),
+// and for FP32 no running sum longer than kMaxSum32 terms (the split partials
+// are added in FP64).  On MI355X at nao=1024, naux=4096, nocc=200 the FP64
+// SYRK took 20.4 / 18.4 / 17.4 / 16.8 / 16.5 ms for about 1024 / 2048 / 4096 /
+// 8192 / 16384 workgroups while the finish, which reads every partial tile,
+// grew from 0.07 ms (2048) to 0.24 (8192) and 0.44 (16384); the FP32 SYRK took
+// 10.3 / 9.45 / 9.24 ms for 2048 / 8192 / 16384 (finish 0.04 / 0.14 / 0.25).
 void syrk_splits(int64_t nrows, int64_t ntl, bool f32, int64_t* nsplit_out, int64_t* kchunk_out) {
-    int64_t nsplit = cdiv(8192, ntl);
+    int64_t nsplit = cdiv(f32 ? 16384 : 8192, ntl);
     if (f32 && nsplit < cdiv(nrows, kMaxSum32)) nsplit = cdiv(nrows, kMaxSum32);
     const int64_t max_split = cdiv(nrows, 256);
     if (nsplit > max_split) nsplit = max_split;
