@@ -583,7 +583,7 @@ int run_gemm1(dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx, bo
 void syrk_splits(int64_t nrows, int64_t ntl, bool f32, int64_t* nsplit_out, int64_t* kchunk_out) {
     int64_t nsplit = cdiv(f32 ? 16384 : 8192, ntl);
     if (f32 && nsplit < cdiv(nrows, kMaxSum32)) nsplit = cdiv(nrows, kMaxSum32);
-    const int64_t max_split = cdiv(nrows, 256);
+    const int64_t max_split = cdiv(nrows, 384);  // splits of at least 384 rows (short contractions)
     if (nsplit > max_split) nsplit = max_split;
     if (nsplit < 1) nsplit = 1;
     const int64_t kchunk = cdiv(cdiv(nrows, nsplit), KC) * KC;
