@@ -254,7 +254,6 @@ def bench_c4(args):
                        "tiles_by_bucket": tiles, "speedup_vs_loop": single / graph,
                        "speedup_vs_untuned": untuned / graph}
         log(name, res_d[name])
-        _ = cache
     res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
            "value": res_d["f32"]["molecules_per_s"], "unit": "molecules/s", "n_gpus": 1,
            "steps": args.steps, "warmup": 1, "ms_per_step": res_d["f32"]["graph_ms"],
