@@ -52,7 +52,9 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64
         L.oracle_rho.argtypes = [dp, i64, i64, i64, dp, dp]
+        L.oracle_rho.restype = ctypes.c_int
         L.oracle_J_acc.argtypes = [dp, i64, i64, i64, dp, dp]
+        L.oracle_J_acc.restype = ctypes.c_int
         L.oracle_K_C_acc.argtypes = [dp, i64, i64, i64, dp, i64, dp]
         L.oracle_K_C_acc.restype = ctypes.c_int
         L.oracle_K_D_acc.argtypes = [dp, i64, i64, i64, dp, dp]
@@ -89,14 +91,16 @@ def rho(B: np.ndarray, nao: int, D: np.ndarray) -> np.ndarray:
     B = _f64(B)
     D = _f64(D)
     out = np.empty(B.shape[0])
-    lib().oracle_rho(_dp(B), B.shape[1], nao, B.shape[0], _dp(D), _dp(out))
+    if lib().oracle_rho(_dp(B), B.shape[1], nao, B.shape[0], _dp(D), _dp(out)) != 0:
+        raise MemoryError("oracle_rho")
     return out
 
 
 def J_acc(B: np.ndarray, nao: int, rho_: np.ndarray, J: np.ndarray) -> None:
     """J += sum_P rho_P B_P over the rows of this block of B."""
     B = _f64(B)
-    lib().oracle_J_acc(_dp(B), B.shape[1], nao, B.shape[0], _dp(_f64(rho_)), _dp(J))
+    if lib().oracle_J_acc(_dp(B), B.shape[1], nao, B.shape[0], _dp(_f64(rho_)), _dp(J)) != 0:
+        raise MemoryError("oracle_J_acc")
 
 
 def J(B: np.ndarray, nao: int, D: np.ndarray, return_rho: bool = False):

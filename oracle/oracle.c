@@ -47,78 +47,89 @@ int oracle_num_threads(void) {
 #endif
 }
 
-/*
- * rho_P = sum_{ka,la} B_P[ka,la] D[ka,la] for each of the nrows rows.
- * B_P is symmetric, so the double sum is taken over the packed pairs
- * ka <= la of row P in storage order, each off-diagonal pair carrying both
- * D[ka,la] and D[la,ka]: the same terms, grouped by pair (exact for any D).
- */
-void oracle_rho(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* D,
-                double* rho) {
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t P = 0; P < nrows; ++P) {
-        const double* Brow = B + P * ldB;
-        double s = 0.0;
-        for (int64_t la = 0; la < nao; ++la)
-            for (int64_t ka = 0; ka <= la; ++ka) {
-                const double b = Brow[pidx(ka, la)];
-                if (ka == la)
-                    s += b * D[la * nao + la];
-                else
-                    s += b * D[ka * nao + la] + b * D[la * nao + ka];
-            }
-        rho[P] = s;
-    }
-}
-
-/*
- * J[mu,nu] += sum_P rho_P B_P[mu,nu] over the nrows rows given.  The sum over
- * P is formed per packed pair (rows of B in order), then written to both
- * (mu,nu) and (nu,mu).
- */
-void oracle_J_acc(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* rho,
-                  double* J) {
-    const int64_t npair = nao * (nao + 1) / 2;
-#pragma omp parallel
-    {
-        const int64_t blk = 4096;
-#pragma omp for schedule(dynamic, 1)
-        for (int64_t p0 = 0; p0 < npair; p0 += blk) {
-            const int64_t p1 = p0 + blk < npair ? p0 + blk : npair;
-            double acc[4096];
-            for (int64_t p = p0; p < p1; ++p) acc[p - p0] = 0.0;
-            for (int64_t P = 0; P < nrows; ++P) {
-                const double* Brow = B + P * ldB;
-                for (int64_t p = p0; p < p1; ++p) acc[p - p0] += rho[P] * Brow[p];
-            }
-            /* write each pair of this block to both triangles */
-            for (int64_t nu = 0; nu < nao; ++nu) {
-                const int64_t base = nu * (nu + 1) / 2;
-                if (base + nu < p0 || base >= p1) continue;
-                for (int64_t mu = 0; mu <= nu; ++mu) {
-                    const int64_t p = base + mu;
-                    if (p < p0 || p >= p1) continue;
-                    J[mu * nao + nu] += acc[p - p0];
-                    if (mu != nu) J[nu * nao + mu] += acc[p - p0];
-                }
-            }
-        }
-    }
-}
-
 /* Unpack one packed row into a full symmetric nao x nao matrix. */
 static void unpack(const double* Brow, int64_t nao, double* full) {
     for (int64_t mu = 0; mu < nao; ++mu)
         for (int64_t nu = 0; nu < nao; ++nu) full[mu * nao + nu] = bval(Brow, mu, nu);
 }
 
-void oracle_unpack(const double* Brow, int64_t nao, double* full) { unpack(Brow, nao, full); }
+/*
+ * rho_P = sum_{ka,la} B_P[ka,la] D[ka,la] for each of the nrows rows: row P
+ * is unpacked to the full B_P, then the double sum runs over the full index
+ * range (any real D).  Returns -1 if scratch memory cannot be had.
+ */
+int oracle_rho(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* D,
+               double* rho) {
+    const int64_t n2 = nao * nao;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* Bf = (double*)malloc((size_t)n2 * sizeof(double));
+        if (!Bf) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t P = 0; P < nrows; ++P) {
+            if (!Bf) continue;
+            unpack(B + P * ldB, nao, Bf);
+            double s = 0.0;
+            for (int64_t ka = 0; ka < nao; ++ka)
+                for (int64_t la = 0; la < nao; ++la) s += Bf[ka * nao + la] * D[ka * nao + la];
+            rho[P] = s;
+        }
+        free(Bf);
+    }
+    return fail ? -1 : 0;
+}
 
 /* Sum thread-private nao x nao accumulators into out, in thread order. */
 static void reduce_private(double* priv, int nt, int64_t n2, double* out) {
     for (int t = 0; t < nt; ++t)
         for (int64_t i = 0; i < n2; ++i) out[i] += priv[(int64_t)t * n2 + i];
 }
+
+/*
+ * J[mu,nu] += sum_P rho_P B_P[mu,nu] over the nrows rows given: each row is
+ * unpacked to the full B_P and rho_P B_P is added over the full index range.
+ * Threads take fixed contiguous ranges of P (static schedule) into private
+ * accumulators that are added in thread order, so the result does not depend
+ * on timing.  Returns -1 if scratch memory cannot be had.
+ */
+int oracle_J_acc(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* rho,
+                 double* J) {
+    const int nt = oracle_num_threads();
+    const int64_t n2 = nao * nao;
+    double* priv = (double*)calloc((size_t)nt * (size_t)n2, sizeof(double));
+    if (!priv) return -1;
+    int fail = 0;
+#pragma omp parallel num_threads(nt)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        double* Jt = priv + (int64_t)t * n2;
+        double* Bf = (double*)malloc((size_t)n2 * sizeof(double));
+        if (!Bf) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(static)
+        for (int64_t P = 0; P < nrows; ++P) {
+            if (!Bf) continue;
+            unpack(B + P * ldB, nao, Bf);
+            for (int64_t mu = 0; mu < nao; ++mu)
+                for (int64_t nu = 0; nu < nao; ++nu) Jt[mu * nao + nu] += rho[P] * Bf[mu * nao + nu];
+        }
+        free(Bf);
+    }
+    if (!fail) reduce_private(priv, nt, n2, J);
+    free(priv);
+    return fail ? -1 : 0;
+}
+
+void oracle_unpack(const double* Brow, int64_t nao, double* full) { unpack(Brow, nao, full); }
 
 /* K[mu,nu] += 2 sum_P sum_i X_P[mu,i] X_P[nu,i],  X_P = B_P C  (D = 2 C C^T). */
 int oracle_K_C_acc(const double* B, int64_t ldB, int64_t nao, int64_t nrows, const double* C,
