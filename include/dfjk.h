@@ -285,8 +285,10 @@ int dfjk_set_tile(dfjk_handle h, int kernel, int index);
  *                       fastest whose K matches the default tile's within
  *                       1e-5 relative, and store the choice in cache_path
  *                       (text lines "dtype bucket tile ms"; read instead of
- *                       timing when present).  best_ms (8 doubles) or NULL.
- *                       Drops a recorded graph.
+ *                       timing when present, and then checked against the
+ *                       default tile's K the same way).  best_ms (8 doubles)
+ *                       or NULL.  Drops a recorded graph first; waits; leaves
+ *                       J and K of every molecule written.
  */
 typedef struct dfjk_batch_ctx* dfjk_batch;
 typedef struct {

@@ -160,6 +160,52 @@ void drop_graph(dfjk_batch_ctx* b) {
     b->graph = nullptr;
 }
 
+// Time every compiled GEMM1 tile on each occupied bucket's launch (best of
+// reps after one warm-up) and keep the fastest per bucket.
+int time_tiles(dfjk_batch_ctx* b, int reps, double* best_ms) {
+    int rc = DFJK_OK;
+    hipEvent_t e0, e1;
+    DFJK_HIP_TRY(hipEventCreate(&e0));
+    DFJK_HIP_TRY(hipEventCreate(&e1));
+    for (int bk = 0; bk < kBuckets; ++bk) {
+        bool present = false;
+        for (const auto& d : b->mols) present |= bucket_of(d.nocc) == bk;
+        if (!present) continue;
+        double best = 1e300;
+        int best_t = b->tile[bk];
+        for (int t = 0; t < k_tile_count(); ++t) {
+            b->tile[bk] = t;
+            if ((rc = build_phases(b))) break;
+            const Phase* ph = nullptr;
+            for (const auto& p : b->phases)
+                if (p.kind < 0 && p.bucket == bk) ph = &p;
+            if (!ph) continue;
+            if ((rc = run_phase(b, *ph, b->stream))) break;  // warm-up
+            double tmin = 1e300;
+            for (int r = 0; r < reps; ++r) {
+                (void)hipEventRecord(e0, b->stream);
+                if ((rc = run_phase(b, *ph, b->stream))) break;
+                (void)hipEventRecord(e1, b->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                tmin = std::min(tmin, (double)ms);
+            }
+            if (rc) break;
+            if (tmin < best) {
+                best = tmin;
+                best_t = t;
+            }
+        }
+        if (rc) break;
+        b->tile[bk] = best_t;
+        if (best_ms) best_ms[bk] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 }  // namespace
 }  // namespace dfjk
 
@@ -378,28 +424,13 @@ int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* 
         return DFJK_E_INVALID;
     }
     int rc;
-    // cached choices for this dtype
-    if (cache_path) {
-        if (FILE* f = fopen(cache_path, "r")) {
-            int dt, bk, t;
-            double ms;
-            int found = 0;
-            while (fscanf(f, "%d %d %d %lf", &dt, &bk, &t, &ms) == 4)
-                if (dt == b->dtype && bk >= 0 && bk < kBuckets && t >= 0 && t < k_tile_count()) {
-                    b->tile[bk] = t;
-                    if (best_ms) best_ms[bk] = ms;
-                    ++found;
-                }
-            fclose(f);
-            if (found) {
-                drop_graph(b);
-                return build_phases(b);
-            }
-        }
-    }
+    // a graph recorded with the old tiles must never replay over new geometry
+    drop_graph(b);
     DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
-    // reference K of every molecule with the current (default) tiles
-    if ((rc = run_all(b, b->stream))) return rc;
+    // reference K of every molecule with the default tiles
+    int default_tile[kBuckets];
+    for (int k = 0; k < kBuckets; ++k) default_tile[k] = b->tile[k] = pick_tile(16 * (k + 1));
+    if ((rc = build_phases(b)) || (rc = run_all(b, b->stream))) return rc;
     DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
     std::vector<std::vector<double>> Kref(b->nmol);
     for (int i = 0; i < b->nmol; ++i) {
@@ -407,48 +438,22 @@ int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* 
         Kref[i].resize((size_t)(d.nao * d.nao));
         DFJK_HIP_TRY(hipMemcpy(Kref[i].data(), d.K, Kref[i].size() * 8, hipMemcpyDeviceToHost));
     }
-    hipEvent_t e0, e1;
-    DFJK_HIP_TRY(hipEventCreate(&e0));
-    DFJK_HIP_TRY(hipEventCreate(&e1));
-    const int default_tile[kBuckets] = {b->tile[0], b->tile[1], b->tile[2], b->tile[3],
-                                        b->tile[4], b->tile[5], b->tile[6], b->tile[7]};
-    for (int bk = 0; bk < kBuckets; ++bk) {
-        bool present = false;
-        for (const auto& d : b->mols) present |= bucket_of(d.nocc) == bk;
-        if (!present) continue;
-        double best = 1e300;
-        int best_t = b->tile[bk];
-        for (int t = 0; t < k_tile_count(); ++t) {
-            b->tile[bk] = t;
-            if ((rc = build_phases(b))) break;
-            const Phase* ph = nullptr;
-            for (const auto& p : b->phases)
-                if (p.kind < 0 && p.bucket == bk) ph = &p;
-            if (!ph) continue;
-            if ((rc = run_phase(b, *ph, b->stream))) break;  // warm-up
-            double tmin = 1e300;
-            for (int r = 0; r < reps; ++r) {
-                (void)hipEventRecord(e0, b->stream);
-                if ((rc = run_phase(b, *ph, b->stream))) break;
-                (void)hipEventRecord(e1, b->stream);
-                (void)hipEventSynchronize(e1);
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                tmin = std::min(tmin, (double)ms);
-            }
-            if (rc) break;
-            if (tmin < best) {
-                best = tmin;
-                best_t = t;
-            }
+    // cached choices for this dtype replace the timing, not the parity check
+    bool cached = false;
+    if (cache_path) {
+        if (FILE* f = fopen(cache_path, "r")) {
+            int dt, bk, t;
+            double ms;
+            while (fscanf(f, "%d %d %d %lf", &dt, &bk, &t, &ms) == 4)
+                if (dt == b->dtype && bk >= 0 && bk < kBuckets && t >= 0 && t < k_tile_count()) {
+                    b->tile[bk] = t;
+                    if (best_ms) best_ms[bk] = ms;
+                    cached = true;
+                }
+            fclose(f);
         }
-        if (rc) break;
-        b->tile[bk] = best_t;
-        if (best_ms) best_ms[bk] = best;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc) return rc;
+    if (!cached && (rc = time_tiles(b, reps, best_ms))) return rc;
     // keep a bucket's choice only if its molecules reproduce the reference K
     if ((rc = build_phases(b)) || (rc = run_all(b, b->stream))) return rc;
     DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
@@ -469,8 +474,7 @@ int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* 
         }
     }
     if (changed && (rc = build_phases(b))) return rc;
-    drop_graph(b);
-    if (cache_path) {
+    if (cache_path && (!cached || changed)) {
         if (FILE* f = fopen(cache_path, "w")) {
             for (int bk = 0; bk < kBuckets; ++bk)
                 fprintf(f, "%d %d %d %.6f\n", b->dtype, bk, b->tile[bk], best_ms ? best_ms[bk] : 0.0);

@@ -45,7 +45,9 @@ def make_batch(pkg, sizes, dtype, seed0):
 
 @pytest.mark.parametrize("dtype", [1, 2])
 def test_batch_matches_oracle(pkg, dtype):
-    sizes = [40, 97, 130, 41, 256, 72, 150, 64, 33, 200]
+    # nocc buckets 0..4 (ceil(nocc/16) - 1), i.e. every bucket the 256-molecule
+    # workload (nao up to 400, nocc up to 80) uses
+    sizes = [40, 97, 130, 41, 256, 72, 150, 64, 33, 200, 345, 400]
     print(f"batch dtype={dtype} sizes={sizes}", flush=True)
     bt, mols, refs = make_batch(pkg, sizes, dtype, 4100)
     bt.build()
@@ -81,17 +83,48 @@ def test_graph_replay_equals_eager(pkg):
     bt.close()
 
 
-def test_autotune_keeps_parity(pkg, tmp_path):
-    sizes = [50, 90, 140, 210]
-    bt, mols, refs = make_batch(pkg, sizes, 2, 4300)
-    cache = str(tmp_path / "tiles.txt")
-    ms = bt.autotune(reps=1, cache_path=cache)
-    print("tiles", [bt.tile(b) for b in range(8)], "ms", ms)
+def _check_all(mols, refs, what):
+    for m, (Bq, C, D) in zip(mols, refs):
+        nao = m["nao"]
+        ej = max_rel(host(m["J"]), oracle.J(Bq, nao, D))
+        ek = max_rel(host(m["K"]), oracle.K_C(Bq, nao, C))
+        assert ej < 1e-10 and ek < 2e-4, (what, nao, ej, ek)
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+def test_autotune_keeps_parity(pkg, tmp_path, dtype):
+    """Default tiles and autotuned tiles over buckets 0..4 (nao up to 380),
+    every molecule against the oracle; a second batch reads the cache (and
+    re-checks those tiles) instead of timing."""
+    sizes = [50, 90, 140, 210, 260, 380]
+    print(f"autotune dtype={dtype} sizes={sizes}", flush=True)
+    bt, mols, refs = make_batch(pkg, sizes, dtype, 4300)
     bt.build()
     torch.cuda.synchronize()
-    for m, (Bq, C, D) in zip(mols, refs):
-        assert max_rel(host(m["K"]), oracle.K_C(Bq, m["nao"], C)) < 2e-4
-    # a second handle reads the cache instead of timing
-    bt2, _, _ = make_batch(pkg, sizes, 2, 4300)
+    _check_all(mols, refs, "default tiles")
+    cache = str(tmp_path / "tiles.txt")
+    ms = bt.autotune(reps=1, cache_path=cache)
+    tiles = [bt.tile(b) for b in range(8)]
+    print("tiles", tiles, "ms", ms)
+    for m in mols:
+        m["J"].zero_()
+        m["K"].zero_()
+    bt.build()
+    torch.cuda.synchronize()
+    _check_all(mols, refs, "tuned tiles")
+    # graph replay of the tuned build equals the eager one
+    eager = [host(m["K"]).copy() for m in mols]
+    bt.capture()
+    bt.launch()
+    torch.cuda.synchronize()
+    for m, K0 in zip(mols, eager):
+        assert np.array_equal(host(m["K"]), K0)
+    bt.close()
+    # a second batch reads the cache instead of timing
+    bt2, mols2, _ = make_batch(pkg, sizes, dtype, 4300)
     bt2.autotune(reps=1, cache_path=cache)
-    assert [bt2.tile(b) for b in range(8)] == [bt.tile(b) for b in range(8)]
+    assert [bt2.tile(b) for b in range(8)] == tiles
+    bt2.build()
+    torch.cuda.synchronize()
+    _check_all(mols2, refs, "cached tiles")
+    bt2.close()
