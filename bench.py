@@ -34,31 +34,86 @@ def k_flops(naux, nao, nocc):
     return 2.0 * naux * nao * nao * nocc, float(naux) * nocc * nao * (nao + 1)
 
 
-def cpu_baseline(cfg, R, C, D, rows: int):
-    """FP64 oracle on the first `rows` auxiliary rows of the same workload."""
+def host_info():
+    """CPU model (lscpu, else /proc/cpuinfo) and the cores this process may use."""
+    import subprocess
+
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+
+
+def _oracle_jk(oracle, B, nao, C, D):
+    """(seconds for J, seconds for K) of one oracle J(D) + K(C) over the rows of B."""
+    t0 = time.perf_counter()
+    r = oracle.rho(B, nao, D)
+    J = np.zeros((nao, nao))
+    oracle.J_acc(B, nao, r, J)
+    tj = time.perf_counter() - t0
+    K = np.zeros((nao, nao))
+    t0 = time.perf_counter()
+    oracle.K_C_acc(B, nao, C, K)
+    return tj, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, R, C, D, rows: int, rows_1t: int = 32):
+    """FP64 oracle on the host: the first `rows` auxiliary rows of the same
+    workload with all threads (median of 3), the first `rows_1t` rows with one
+    thread, and the nao=64 workload in full with one thread and with all
+    (median of 3 each)."""
     import oracle
     import synth
 
+    threads = oracle.num_threads()
     B = synth.B_rows(cfg.seed, R, 0, rows)
-    t0 = time.perf_counter()
-    r = oracle.rho(B, cfg.nao, D)
-    J = np.zeros((cfg.nao, cfg.nao))
-    oracle.J_acc(B, cfg.nao, r, J)
-    tj = time.perf_counter() - t0
-    K = np.zeros((cfg.nao, cfg.nao))
-    t0 = time.perf_counter()
-    oracle.K_C_acc(B, cfg.nao, C, K)
-    tk = time.perf_counter() - t0
+    runs = [_oracle_jk(oracle, B, cfg.nao, C, D) for _ in range(3)]
+    tj = float(np.median([r[0] for r in runs]))
+    tk = float(np.median([r[1] for r in runs]))
     g1, sy = k_flops(rows, cfg.nao, cfg.nocc)
+    oracle.set_num_threads(1)
+    try:
+        tj1, tk1 = _oracle_jk(oracle, B[:rows_1t], cfg.nao, C, D)
+        c1 = synth.C1
+        R1 = synth.positions(c1)
+        B1 = synth.B_full(c1.seed, R1, c1.naux)
+        C1 = synth.C_occ(c1.seed, c1.nao, c1.nocc)
+        D1 = 2.0 * C1 @ C1.T
+        c1_1t = float(np.median([sum(_oracle_jk(oracle, B1, c1.nao, C1, D1)) for _ in range(3)]))
+    finally:
+        oracle.set_num_threads(threads)
+    c1_all = float(np.median([sum(_oracle_jk(oracle, B1, c1.nao, C1, D1)) for _ in range(3)]))
+    g1_1t, sy_1t = k_flops(rows_1t, cfg.nao, cfg.nocc)
     return {
         "value": (g1 + sy) / tk / 1e12,
         "unit": "TFLOP/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"K(C_occ) and J over aux rows 0..{rows - 1} of {cfg.naux} (nao={cfg.nao}, "
-                  f"nocc={cfg.nocc}, FP64); K {tk:.2f} s, J {tj:.2f} s",
+                  f"nocc={cfg.nocc}, FP64), median of 3: K {tk:.2f} s, J {tj:.2f} s",
         "j_gbs": 2 * rows * cfg.npair * 8 / tj / 1e9,
-        "seconds": tk + tj,
+        "seconds": 3 * (tk + tj),
+        **host_info(),
+        "one_thread": {
+            "k_tflops": (g1_1t + sy_1t) / tk1 / 1e12, "j_gbs": 2 * rows_1t * cfg.npair * 8 / tj1 / 1e9,
+            "sample": f"aux rows 0..{rows_1t - 1}, one run: K {tk1:.2f} s, J {tj1:.2f} s"},
+        "nao64_jk_seconds": {"one_thread_median_of_3": c1_1t, "all_threads_median_of_3": c1_all,
+                             "workload": f"nao={synth.C1.nao}, naux={synth.C1.naux}, "
+                                         f"nocc={synth.C1.nocc}, one J + one K"},
     }
 
 
@@ -94,16 +149,93 @@ def time_steps(pkg, h, Dd, Cd, cfg, steps, warmup):
     torch.cuda.synchronize()
     pkg.dfjk_profile(h.h, max(steps, 1))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
     e0.record()
-    for _ in range(steps):
+    for a, b, c in ev:
+        a.record()
         pkg.dfjk_build_J(h.h, Dd, J)
+        b.record()
         pkg.dfjk_build_K(h.h, Cd, cfg.nocc, None, K)
+        c.record()
     e1.record()
     torch.cuda.synchronize()
     prof = pkg.dfjk_profile_read(h.h)
     pkg.dfjk_profile(h.h, 0)
     return {"ms_per_step": e0.elapsed_time(e1) / steps,
+            "median_ms": {"step": float(np.median([a.elapsed_time(c) for a, b, c in ev])),
+                          "J": float(np.median([a.elapsed_time(b) for a, b, c in ev])),
+                          "K": float(np.median([b.elapsed_time(c) for a, b, c in ev]))},
             "phase_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()}}
+
+
+class C3CpuLeg:
+    """CPU-baseline leg of the nao=2048 workload: the FP64 oracle streams the
+    same row blocks as the device copy is made (rho and J over every auxiliary
+    row, timed), then builds the whole K of the first `slice_rows` rows in FP64
+    and on those rows rounded to each stored format (timed).  Each GPU result
+    is stated against it: (i) the oracle on the FP64 B, (ii) the oracle on the
+    rounded B."""
+
+    def __init__(self, cfg, C, D, slice_rows: int = 64):
+        import oracle
+
+        self.o, self.cfg, self.C, self.D, self.ns = oracle, cfg, C, D, slice_rows
+        self.rho = np.empty(cfg.naux)
+        self.J = np.zeros((cfg.nao, cfg.nao))
+        self.t_j = 0.0
+        self.slice_B = None
+
+    def feed(self, P0: int, blk: np.ndarray) -> None:
+        t0 = time.perf_counter()
+        r = self.o.rho(blk, self.cfg.nao, self.D)
+        self.o.J_acc(blk, self.cfg.nao, r, self.J)
+        self.t_j += time.perf_counter() - t0
+        self.rho[P0:P0 + blk.shape[0]] = r
+        if P0 == 0:
+            self.slice_B = np.ascontiguousarray(blk[:self.ns])
+
+    def slice_refs(self, name: str):
+        """Oracle J, rho and K of the slice system: FP64 rows (i) and rows
+        rounded to `name` (ii); for the 16-bit exchange option also with C
+        rounded to `name` (ii')."""
+        o, nao, C, D = self.o, self.cfg.nao, self.C, self.D
+        q = {"bf16": o.quantize_bf16, "f16": o.quantize_f16}[name]
+        out = {}
+        t0 = time.perf_counter()
+        for key, Bs, Cs in [("i", self.slice_B, C), ("ii", q(self.slice_B), C), ("ii_k16", None, q(C))]:
+            Bs = out["ii"][3] if Bs is None else Bs
+            Jr, rr = o.J(Bs, nao, D, return_rho=True)
+            out[key] = (Jr, rr, o.K_C(Bs, nao, Cs), Bs)
+        self.t_k = time.perf_counter() - t0
+        return out
+
+    def report(self, name: str, gpu: dict) -> dict:
+        """Errors of the GPU results `gpu` (J, rho over all rows; J, rho, K,
+        K16 of the slice) against the oracle."""
+        def frob(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+        def e2(rho_, K_):
+            return 0.5 * float(rho_ @ rho_) - 0.25 * float(np.sum(self.D * K_))
+
+        ref = self.slice_refs(name)
+        J, rho = gpu["J"], gpu["rho"]
+        ej, ej_o = 0.5 * float(rho @ rho), 0.5 * float(self.rho @ self.rho)
+        res = {"J_frob_i": frob(J, self.J), "J_maxrel_i": float(np.abs(J - self.J).max() / np.abs(self.J).max()),
+               "E_J_Eh": ej_o, "E_J_err_i_Eh": ej - ej_o}
+        sl = {"aux_rows": self.ns}
+        for key in ("i", "ii"):
+            Jr, rr, Kr, _ = ref[key]
+            sl[f"J_frob_{key}"] = frob(gpu["J_s"], Jr)
+            sl[f"K_frob_{key}"] = frob(gpu["K_s"], Kr)
+            sl[f"E_2e_err_{key}_Eh"] = e2(gpu["rho_s"], gpu["K_s"]) - e2(rr, Kr)
+        sl["E_2e_Eh"] = e2(ref["i"][1], ref["i"][2])
+        sl["k16"] = {"K_frob_i": frob(gpu["K16_s"], ref["i"][2]),
+                     "K_frob_ii_C_rounded": frob(gpu["K16_s"], ref["ii_k16"][2]),
+                     "E_2e_err_i_Eh": e2(gpu["rho_s"], gpu["K16_s"]) - e2(ref["i"][1], ref["i"][2]),
+                     "E_2e_err_ii_Eh": e2(gpu["rho_s"], gpu["K16_s"]) - e2(ref["ii_k16"][1], ref["ii_k16"][2])}
+        res["slice"] = sl
+        return res
 
 
 def bench_c3(args):
@@ -124,15 +256,20 @@ def bench_c3(args):
     bufs = {}
     for name, code, tdt in [("bf16", pkg.DFJK_BF16, torch.bfloat16), ("f16", pkg.DFJK_F16, torch.float16)]:
         bufs[name] = (code, torch.empty((cfg.naux, cfg.npair), dtype=tdt, device="cuda"))
+    cpu = C3CpuLeg(cfg, C, D) if args.cpu_rows > 0 else None
     t0 = time.time()
     rows = 512
     for P0 in range(0, cfg.naux, rows):
-        blk = torch.from_numpy(synth.B_rows(cfg.seed, R, P0, rows)).cuda()
+        host_blk = synth.B_rows(cfg.seed, R, P0, rows)
+        blk = torch.from_numpy(host_blk).cuda()
         for name, (code, buf) in bufs.items():
             pkg.dfjk_quantize(blk, buf[P0:P0 + rows], code, blk.numel())
+        if cpu is not None:
+            cpu.feed(P0, host_blk)
         torch.cuda.synchronize()
         log(f"  rows {P0 + rows}/{cfg.naux} after {time.time() - t0:.0f} s")
-    del blk
+    del blk, host_blk
+    gpu_out = {}
     for name, (code, buf) in bufs.items():
         h = pkg.Handle(buf, cfg.nao, dtype=code)
         r = time_steps(pkg, h, Dd, Cd, cfg, args.steps, args.warmup)
@@ -142,6 +279,24 @@ def bench_c3(args):
                      "ms_per_step": r["ms_per_step"], "phase_ms": ph,
                      "k_gemm1_frac_of_f32_peak": g1_flops / ph["K_gemm1"] / 1e9 / PEAK["f32"],
                      "j_frac_of_hbm": jb / ph["J"] / 1e6 / PEAK["hbm_gbs"]}
+        if cpu is not None:  # results whose errors the CPU leg states
+            Jt = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+            rt = torch.empty(cfg.naux, dtype=torch.float64, device="cuda")
+            pkg.dfjk_build_J(h.h, Dd, Jt, rt)
+            g = {"J": Jt.cpu().numpy(), "rho": rt.cpu().numpy()}
+            ns = cpu.ns
+            for key, k16 in (("", 0), ("16", 1)):
+                o = pkg.dfjk.default_options()
+                o.k16 = k16
+                hs = pkg.Handle(buf[:ns], cfg.nao, dtype=code, opts=o)
+                rs = torch.empty(ns, dtype=torch.float64, device="cuda")
+                pkg.dfjk_build_J(hs.h, Dd, Jt, rs)
+                g["J_s"], g["rho_s"] = Jt.cpu().numpy(), rs.cpu().numpy()
+                pkg.dfjk_build_K(hs.h, Cd, cfg.nocc, None, Jt)
+                g[f"K{key}_s"] = Jt.cpu().numpy()
+                hs.close()
+            gpu_out[name] = g
+            del Jt, rt
         h.close()
         # the same build with K on the 16-bit matrix cores (dense 16-bit copy of B)
         opts = pkg.dfjk.default_options()
@@ -173,6 +328,19 @@ def bench_c3(args):
                                   f"matrix cores (k16: on 16-bit matrix cores)", "nao": cfg.nao,
                       "naux": cfg.naux, "nocc": cfg.nocc},
            "bf16": out["bf16"], "f16": out["f16"]}
+    if cpu is not None:
+        for name in ("bf16", "f16"):
+            res[name]["errors_vs_fp64_oracle"] = cpu.report(name, gpu_out[name])
+        res["cpu_baseline"] = {
+            "value": 2.0 * cfg.naux * cfg.npair * 8 / cpu.t_j / 1e9, "unit": "GB/s (J, FP64 B)",
+            "cores": cpu.o.num_threads(), "kind": "oracle", **host_info(),
+            "sample": f"rho and J over all {cfg.naux} aux rows in FP64 ({cpu.t_j:.1f} s, streamed in "
+                      f"512-row blocks); K of the first {cpu.ns} rows three times (FP64, rounded B, "
+                      f"rounded B and C) in {cpu.t_k:.1f} s",
+            "k_tflops": 3 * sum(k_flops(cpu.ns, cfg.nao, cfg.nocc)) / cpu.t_k / 1e12}
+        res["errors_note"] = ("(i) against the FP64 oracle on the FP64 B, (ii) against the FP64 oracle on the "
+                              "rounded B; J and E_J over all rows, the rest on the system of the first "
+                              f"{cpu.ns} auxiliary rows (whole J, K and E_2e = E_J + E_K)")
     print(json.dumps(res), flush=True)
 
 
@@ -504,7 +672,7 @@ def main():
                     help="c5: scale of B in the SCF family (default: the generator's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
-    ap.add_argument("--cpu-rows", type=int, default=1024,
+    ap.add_argument("--cpu-rows", type=int, default=512,
                     help="aux rows in the CPU-oracle sample (0 = skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -575,13 +743,22 @@ def main():
     torch.cuda.synchronize()
     pkg.dfjk_profile(h.h, max(args.steps, 1))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # per-step events on the handle's stream (torch's current stream) around J and K
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    for a, b, c in ev:
+        a.record()
+        pkg.dfjk_build_J(h.h, Dd, J)
+        b.record()
+        pkg.dfjk_build_K(h.h, Cd, cfg.nocc, None, K)
+        c.record()
     e1.record()
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
+    med = {"step": float(np.median([a.elapsed_time(c) for a, b, c in ev])),
+           "J": float(np.median([a.elapsed_time(b) for a, b, c in ev])),
+           "K": float(np.median([b.elapsed_time(c) for a, b, c in ev]))}
     prof = pkg.dfjk_profile_read(h.h)
     log("per-phase event totals (ms, launches):", prof)
 
@@ -598,7 +775,7 @@ def main():
     traffic = counter_traffic(f"c2-{args.dtype}".replace("-", "_"))
     res = {
         "metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
-        "value": (g1_flops + sy_flops) / k_ms / 1e9,
+        "value": (g1_flops + sy_flops) / med["K"] / 1e9,
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -615,7 +792,11 @@ def main():
                         f"K(C_occ) build per step",
             "nao": cfg.nao, "naux": cfg.naux, "nocc": cfg.nocc, "B_dtype": args.dtype,
         },
-        "j_hbm_gbs": jbytes / j_ms / 1e6,
+        "timing": f"value = algorithmic K flop / median of {args.steps} per-step K times (HIP events on the "
+                  f"handle's stream); phase_ms and roofline = per-launch averages from the library's own events",
+        "median_ms": med,
+        "k_tflops_mean": (g1_flops + sy_flops) / k_ms / 1e9,
+        "j_hbm_gbs": jbytes / med["J"] / 1e6,
         "jk_builds_per_s": 1000.0 / (total_ms / args.steps),
         "phase_ms": {"J": j_ms, "J_rho": jr_ms, "J_out": jo_ms, "K": k_ms, "K_gemm1": g1_ms,
                      "K_syrk": sy_ms, "K_finish": avg("K_finish")},

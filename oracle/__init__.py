@@ -63,6 +63,8 @@ def lib():
         L.oracle_K_C_rows.argtypes = [dp, i64, i64, i64, dp, i64, dp]
         L.oracle_K_C_rows.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -78,6 +80,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for the following oracle calls."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def nao_of(ldB_or_npair: int) -> int:

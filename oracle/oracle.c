@@ -47,6 +47,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads for the following calls (timing runs at one thread and at all). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Unpack one packed row into a full symmetric nao x nao matrix. */
 static void unpack(const double* Brow, int64_t nao, double* full) {
     for (int64_t mu = 0; mu < nao; ++mu)
