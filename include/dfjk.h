@@ -25,7 +25,8 @@
  * of the handle and never writes it (with the k16 option the handle also keeps
  * a dense 16-bit copy of it).  The handle owns its workspace, which
  * it allocates in dfjk_init and, when a call needs more (a larger nocc),
- * in that call.
+ * in that call -- unless dfjk_options.max_ncol > 0, which reserves all of it
+ * in dfjk_init.
  *
  * Streams: every call enqueues its work on the stream given to dfjk_init
  * and returns without waiting, except where stated.
@@ -76,9 +77,24 @@ typedef struct {
                              1 = compensated FP32 (Dot2), 0 = plain FP32 */
     int k16;              /* BF16/FP16 B, exchange from C: 1 = 16-bit matrix cores
                              (the handle keeps a dense 16-bit copy of B, naux *
-                             ceil32(nao)^2 elements, made on the first K call; C
+                             ceil64(nao)^2 elements, made in dfjk_init when
+                             max_ncol > 0, else on the first K call; K then
+                             uses B's contents as they were when the copy was
+                             made: call dfjk_update_B after changing them; C
                              and X rounded to the 16-bit format); 0 = B
                              dequantised on load, FP32 matrix cores (default) */
+    int max_ncol;         /* 0 (default): workspace grows on demand, so a call
+                             may allocate.  1..nao: dfjk_init reserves every
+                             workspace buffer for K with up to max_ncol columns
+                             of C (two-factor K: up to max_ncol / 2; K from a
+                             density, and SCF steps without valid Cocc, need
+                             max_ncol = nao), J of up to max_ndm densities at
+                             a time, the DF diagonal and the SCF state; later
+                             calls never allocate (they can be captured in a
+                             HIP graph), and one that would need more returns
+                             DFJK_E_INVALID before enqueuing anything */
+    int max_ndm;          /* densities per dfjk_build_J_multi pass reserved
+                             with max_ncol > 0 (8; at most 8 are used) */
 } dfjk_options;
 
 /* Fills *o with the defaults. */
@@ -359,6 +375,15 @@ int dfjk_probe_mfma(int dtype, double* tflops);
  * buffer or fewer than 16 bytes.
  */
 int dfjk_probe_hbm_read(const void* buf_dev, size_t bytes, double* gbs);
+
+/*
+ * Tell the handle that the contents of B changed (same pointer, layout and
+ * dtype).  J and K read B on every call, except the k16 exchange, which
+ * reads the handle's dense 16-bit copy: this remakes that copy (no
+ * allocation; asynchronous on the handle's stream).  A no-op for handles
+ * without a copy.
+ */
+int dfjk_update_B(dfjk_handle h);
 
 /* Device workspace currently held by the handle, in bytes. */
 int dfjk_workspace_bytes(dfjk_handle h, size_t* bytes);

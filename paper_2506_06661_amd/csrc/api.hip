@@ -20,6 +20,11 @@ void clear_error() { g_err[0] = 0; }
 
 int DevBuf::ensure(size_t want) {
     if (want <= bytes && ptr) return DFJK_OK;
+    if (fixed) {
+        set_error("the call needs %zu bytes of a workspace buffer reserved at init with %zu "
+                  "(raise max_ncol / max_ndm in dfjk_options)", want, bytes);
+        return DFJK_E_INVALID;
+    }
     release();
     if (want == 0) want = 256;
     if (hipMalloc(&ptr, want) != hipSuccess) {
@@ -37,6 +42,35 @@ void DevBuf::release() {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
+}
+
+// Reserve every workspace buffer for the sizes the options allow, make the
+// 16-bit copy of B if the handle uses one, then fix the buffers so that no
+// later call allocates.
+static int reserve_all(dfjk_ctx* h) {
+    int rc;
+    if ((rc = j_reserve(h, h->opts.max_ndm))) return rc;
+    if ((rc = k_reserve(h, h->opts.max_ncol))) return rc;
+    if ((h->dtype == DFJK_BF16 || h->dtype == DFJK_F16) && h->opts.k16) {
+        if ((rc = k16_reserve(h, h->opts.max_ncol))) return rc;
+        if ((rc = k16_make_dense(h))) return rc;
+    }
+    if (h->nao <= 4096 && (rc = scf_reserve(h))) return rc;
+    DevBuf* all[] = {&h->dt, &h->rho_part, &h->rho, &h->jpart, &h->dpart, &h->mdt, &h->mpart, &h->mrho,
+                     &h->mjpart, &h->X, &h->kpart, &h->ones, &h->Cw, &h->eig, &h->Bdense};
+    for (DevBuf* b : all) b->fixed = true;
+    return DFJK_OK;
+}
+
+// With workspace reserved at init, a call whose K needs more factor columns
+// than reserved is refused before anything is enqueued.
+static int check_reserved(const dfjk_ctx* h, int64_t ncol, const char* what) {
+    if (h->opts.max_ncol > 0 && ncol > h->opts.max_ncol) {
+        set_error("%s: needs workspace for %lld factor columns, the handle reserved %d (max_ncol)", what,
+                  (long long)ncol, h->opts.max_ncol);
+        return DFJK_E_INVALID;
+    }
+    return DFJK_OK;
 }
 
 static int check_handle(const dfjk_ctx* h) {
@@ -61,6 +95,8 @@ void dfjk_default_options(dfjk_options* o) {
     o->max_cycle = 100;
     o->compensated_j = 2;
     o->k16 = 0;
+    o->max_ncol = 0;
+    o->max_ndm = 8;
 }
 
 const char* dfjk_last_error(void) { return g_err; }
@@ -90,6 +126,17 @@ int dfjk_init(dfjk_handle* out, const void* B_dev, int dtype, int64_t nao, int64
         set_error("dfjk_init: ldB=%lld < nao(nao+1)/2=%lld", (long long)ldB, (long long)npair);
         return DFJK_E_INVALID;
     }
+    dfjk_options o;
+    if (opts)
+        o = *opts;
+    else
+        dfjk_default_options(&o);
+    if (o.diis_space < 1 || o.diis_space > 15 || o.max_cycle < 1 || o.compensated_j < 0 || o.compensated_j > 2 ||
+        o.k16 < 0 || o.k16 > 1 || o.max_ncol < 0 || o.max_ncol > nao || o.max_ndm < 1) {
+        set_error("dfjk_init: options out of range (diis_space 1..15, compensated_j 0..2, k16 0..1, "
+                  "max_ncol 0..nao, max_ndm >= 1)");
+        return DFJK_E_INVALID;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -113,23 +160,22 @@ int dfjk_init(dfjk_handle* out, const void* B_dev, int dtype, int64_t nao, int64
     h->naux = naux;
     h->ldB = ldB;
     h->npair = npair;
-    if (opts)
-        h->opts = *opts;
-    else
-        dfjk_default_options(&h->opts);
-    if (h->opts.diis_space < 1 || h->opts.diis_space > 15 || h->opts.max_cycle < 1 ||
-        h->opts.compensated_j < 0 || h->opts.compensated_j > 2 || h->opts.k16 < 0 || h->opts.k16 > 1) {
-        delete h;
-        set_error("dfjk_init: options out of range (diis_space 1..15, compensated_j 0..2)");
-        return DFJK_E_INVALID;
-    }
+    h->opts = o;
     int rc = j_setup(h);
+    if (rc == DFJK_OK && h->opts.max_ncol > 0) rc = reserve_all(h);
     if (rc != DFJK_OK) {
         dfjk_destroy(h);
         return rc;
     }
     *out = h;
     return DFJK_OK;
+}
+
+int dfjk_update_B(dfjk_handle h) {
+    clear_error();
+    if (int rc = check_handle(h)) return rc;
+    if (!h->dense_ready) return DFJK_OK;  // nothing derived from B's contents yet
+    return k16_make_dense(h);
 }
 
 int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev) {
@@ -190,6 +236,7 @@ int dfjk_build_K_factored(dfjk_handle h, const double* C_dev, int64_t ncol, cons
                   (long long)h->nao);
         return DFJK_E_INVALID;
     }
+    if (int rc = check_reserved(h, ncol, "dfjk_build_K_factored")) return rc;
     return k_build_factored(h, C_dev, ncol, sign_dev, scale, K_dev);
 }
 
@@ -209,6 +256,7 @@ int dfjk_build_K_pair(dfjk_handle h, const double* L_dev, const double* R_dev, i
         set_error("dfjk_build_K_pair: sym=%d is neither 0 nor 1", sym);
         return DFJK_E_INVALID;
     }
+    if (int rc = check_reserved(h, 2 * ncol, "dfjk_build_K_pair")) return rc;
     return k_build_pair(h, L_dev, R_dev, ncol, sym, scale, K_dev);
 }
 
@@ -226,12 +274,14 @@ int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const doub
                       (long long)h->nao);
             return DFJK_E_INVALID;
         }
+        if (int rc = check_reserved(h, nocc, "dfjk_build_K")) return rc;
         return k_build_factored(h, Cocc_dev, nocc, nullptr, 2.0, K_dev);
     }
     if (!D_dev) {
         set_error("dfjk_build_K: both Cocc and D are null");
         return DFJK_E_INVALID;
     }
+    if (int rc = check_reserved(h, h->nao, "dfjk_build_K (from D)")) return rc;
     return k_build_from_D(h, D_dev, K_dev);
 }
 
@@ -252,6 +302,7 @@ int dfjk_scf_step(dfjk_handle h, const double* H_dev, double* D_dev, double* Coc
         set_error("dfjk_scf_step: unknown flags 0x%x", flags);
         return DFJK_E_INVALID;
     }
+    if (int rc = check_reserved(h, (flags & DFJK_SCF_C_VALID) ? nocc : h->nao, "dfjk_scf_step")) return rc;
     return scf_step(h, H_dev, D_dev, Cocc_dev, nocc, flags, info);
 }
 

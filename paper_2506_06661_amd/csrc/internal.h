@@ -34,11 +34,14 @@ void clear_error();
         }                                                                                         \
     } while (0)
 
-// Grow-only device buffer owned by a handle.
+// Grow-only device buffer owned by a handle.  Once `fixed` (workspace
+// reserved at init), ensure() never allocates: a larger request fails with
+// DFJK_E_INVALID.
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
-    int ensure(size_t want);  // returns DFJK_OK / DFJK_E_OOM
+    bool fixed = false;
+    int ensure(size_t want);  // returns DFJK_OK / DFJK_E_OOM / DFJK_E_INVALID
     void release();
 };
 
@@ -103,11 +106,24 @@ struct dfjk_ctx {
 namespace dfjk {
 
 // J launchers (j_kernels.hip)
+struct JWork {  // bytes of each J workspace buffer for a handle's sizes
+    size_t dt, rho_part, rho, jpart;
+};
+void j_plan(dfjk_ctx* h, JWork* w);  // also sets h->j_chunks, h->j_splits
+int64_t j_splits_used(const dfjk_ctx* h);  // pass-2 row slices j_build uses (after j_plan)
 int j_setup(dfjk_ctx* h);
 int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* diag);
 int j_build_multi(dfjk_ctx* h, int64_t ndm, const double* D, double* J, double* rho_out);
 int form_B(int64_t naux, int64_t ncol, double* M, double* Q, int64_t ldQ, hipStream_t st);
 int j_out_count();
+
+// Workspace reservation at init (options max_ncol > 0): each build path
+// sizes its buffers with the same function it uses when it runs.
+int j_reserve(dfjk_ctx* h, int64_t max_ndm);
+int k_reserve(dfjk_ctx* h, int64_t max_ncol);
+int k16_reserve(dfjk_ctx* h, int64_t max_ncol);
+int k16_make_dense(dfjk_ctx* h);
+int scf_reserve(dfjk_ctx* h);
 
 // K launchers (k_kernels.hip)
 int k_build_factored(dfjk_ctx* h, const double* C, int64_t ncol, const double* sign, double scale,

@@ -768,7 +768,7 @@ static void j_out_geometry(const dfjk_ctx* h, int U, int64_t* splits_out) {
 
 int j_out_count() { return kNumJOut; }
 
-int j_setup(dfjk_ctx* h) {
+void j_plan(dfjk_ctx* h, JWork* w) {
     const int64_t rowblocks = cdiv(h->naux, kRhoRows);
     // pass 1: enough (row block, chunk) workgroups to cover the chip several times
     int64_t chunks = cdiv(4096, rowblocks);
@@ -785,11 +785,33 @@ int j_setup(dfjk_ctx* h) {
         if (sp > splits) splits = sp;
     }
     h->j_splits = (int)splits;
+    w->dt = sizeof(double) * (size_t)h->npair * 3;  // FP64 packed density + FP32 hi/lo
+    w->rho_part = sizeof(double) * (size_t)h->naux * (size_t)chunks;
+    w->rho = sizeof(double) * (size_t)h->naux * 2;  // rho + FP32 hi/lo
+    w->jpart = sizeof(double) * (size_t)h->npair * (size_t)splits;
+}
+
+int64_t j_splits_used(const dfjk_ctx* h) {
+    if (h->dtype != DFJK_F64) return h->j_splits;
+    const int t = h->jout_tile >= 0 && h->jout_tile < kNumJOut ? h->jout_tile : 1;
+    int64_t splits;
+    j_out_geometry(h, kJOutU[t], &splits);
+    return splits;
+}
+
+// DF-diagonal partials (one row slice of npair sums per pass-2 split)
+static size_t j_diag_bytes(const dfjk_ctx* h) {
+    return sizeof(double) * (size_t)h->npair * (size_t)(h->dtype == DFJK_F64 ? j_splits_used(h) : h->j_splits);
+}
+
+int j_setup(dfjk_ctx* h) {
+    JWork w;
+    j_plan(h, &w);
     int rc;
-    if ((rc = h->dt.ensure(sizeof(double) * (size_t)h->npair * 3))) return rc;
-    if ((rc = h->rho_part.ensure(sizeof(double) * (size_t)h->naux * (size_t)chunks))) return rc;
-    if ((rc = h->rho.ensure(sizeof(double) * (size_t)h->naux * 2))) return rc;  // rho + FP32 hi/lo
-    if ((rc = h->jpart.ensure(sizeof(double) * (size_t)h->npair * (size_t)splits))) return rc;
+    if ((rc = h->dt.ensure(w.dt))) return rc;
+    if ((rc = h->rho_part.ensure(w.rho_part))) return rc;
+    if ((rc = h->rho.ensure(w.rho))) return rc;
+    if ((rc = h->jpart.ensure(w.jpart))) return rc;
     return DFJK_OK;
 }
 
@@ -838,7 +860,7 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* di
     double* dpart = nullptr;
     if (diag) {
         int rc;
-        if ((rc = h->dpart.ensure(sizeof(double) * (size_t)h->npair * (size_t)splits))) return rc;
+        if ((rc = h->dpart.ensure(j_diag_bytes(h)))) return rc;
         dpart = static_cast<double*>(h->dpart.ptr);
     }
     h->prof.begin(PH_J_OUT, st);
@@ -860,6 +882,40 @@ int j_build(dfjk_ctx* h, const double* D, double* J, double* rho_out, double* di
     return DFJK_OK;
 }
 
+// several-density geometry: pass 1 (8-row block, chunk) workgroups covering
+// the chip several times; pass 2 1024 columns per workgroup
+static void j_multi_geometry(const dfjk_ctx* h, int64_t* nchunk_out, int64_t* nsplit_out) {
+    const int64_t rowblocks = cdiv(h->naux, kRhoRowsM);
+    int64_t nchunk = cdiv(4096, rowblocks);
+    const int64_t max_chunks = cdiv(h->npair, 2 * kThreads * 4);
+    if (nchunk > max_chunks) nchunk = max_chunks;
+    if (nchunk < 1) nchunk = 1;
+    *nchunk_out = nchunk;
+    j_out_geometry(h, 2, nsplit_out);
+}
+
+static int j_multi_ensure(dfjk_ctx* h, int64_t mmax, int64_t nchunk, int64_t nsplit) {
+    const int64_t naux = h->naux, npair = h->npair;
+    int rc;
+    if ((rc = h->mdt.ensure(sizeof(double) * (size_t)(mmax * npair))) ||
+        (rc = h->mpart.ensure(sizeof(double) * (size_t)(mmax * naux * nchunk))) ||
+        (rc = h->mrho.ensure(sizeof(double) * (size_t)(mmax * naux))) ||
+        (rc = h->mjpart.ensure(sizeof(double) * (size_t)(mmax * nsplit * npair))))
+        return rc;
+    return DFJK_OK;
+}
+
+int j_reserve(dfjk_ctx* h, int64_t max_ndm) {
+    int rc;
+    // the pass-2 width may be changed later with dfjk_set_tile: reserve the
+    // DF-diagonal partials for the widest split count any width uses
+    if ((rc = h->dpart.ensure(sizeof(double) * (size_t)h->npair * (size_t)h->j_splits))) return rc;
+    if (h->dtype != DFJK_F64) return DFJK_OK;  // reduced B: one density at a time, no extra buffers
+    int64_t nchunk, nsplit;
+    j_multi_geometry(h, &nchunk, &nsplit);
+    return j_multi_ensure(h, max_ndm < kMaxDm ? max_ndm : kMaxDm, nchunk, nsplit);
+}
+
 int j_build_multi(dfjk_ctx* h, int64_t ndm, const double* D, double* J, double* rho_out) {
     const int64_t nao = h->nao, naux = h->naux, npair = h->npair;
     if (h->dtype != DFJK_F64) {  // reduced B: one J stream per density
@@ -874,23 +930,13 @@ int j_build_multi(dfjk_ctx* h, int64_t ndm, const double* D, double* J, double* 
     const double* B = static_cast<const double*>(h->B);
     const bool vec = (h->ldB % 2 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
     const int64_t mmax = ndm < kMaxDm ? ndm : kMaxDm;
-    // pass 1 geometry: (8-row block, chunk) workgroups covering the chip several times
     const int64_t rowblocks = cdiv(naux, kRhoRowsM);
-    int64_t nchunk = cdiv(4096, rowblocks);
-    const int64_t max_chunks = cdiv(npair, 2 * kThreads * 4);
-    if (nchunk > max_chunks) nchunk = max_chunks;
-    if (nchunk < 1) nchunk = 1;
+    int64_t nchunk, nsplit;
+    j_multi_geometry(h, &nchunk, &nsplit);
     int64_t chunk = cdiv(cdiv(npair, nchunk), 2) * 2;
-    // pass 2 geometry: 1024 columns per workgroup
-    int64_t nsplit;
-    j_out_geometry(h, 2, &nsplit);
     const int64_t prows = cdiv(naux, nsplit);
     int rc;
-    if ((rc = h->mdt.ensure(sizeof(double) * (size_t)(mmax * npair))) ||
-        (rc = h->mpart.ensure(sizeof(double) * (size_t)(mmax * naux * nchunk))) ||
-        (rc = h->mrho.ensure(sizeof(double) * (size_t)(mmax * naux))) ||
-        (rc = h->mjpart.ensure(sizeof(double) * (size_t)(mmax * nsplit * npair))))
-        return rc;
+    if ((rc = j_multi_ensure(h, mmax, nchunk, nsplit))) return rc;
     double* dt = static_cast<double*>(h->mdt.ptr);
     double* part = static_cast<double*>(h->mpart.ptr);
     double* rho = static_cast<double*>(h->mrho.ptr);

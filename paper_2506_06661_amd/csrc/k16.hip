@@ -643,23 +643,61 @@ constexpr int kSyrk16Tiles[] = {128, 256};
 constexpr int kNumSyrk16Tiles = 2;
 inline int pick_syrk16_tile(int64_t nao) { return nao >= 1024 ? 1 : 0; }
 
+// Dense row length of the 16-bit copy (64-deep chunks) and the GEMM2 split:
+// about 2048 workgroups, and no FP32 running sum longer than kMaxSum16 terms
+// (the split partials are added in FP64).
+inline int64_t k16_ldd(int64_t nao) { return cdiv(nao, KC16) * KC16; }
+
+struct K16Plan {
+    int64_t ncp, T, ntl, nsplit, pchunk;
+    size_t Bdense, Cw, X, kpart;  // bytes
+};
+
+K16Plan k16_plan(const dfjk_ctx* h, int64_t ncol) {
+    K16Plan p;
+    const int64_t nao = h->nao, naux = h->naux, ldd = k16_ldd(nao);
+    p.ncp = cdiv(ncol, KS) * KS;
+    int ts = h->k16_syrk_tile;
+    if (ts < 0 || ts >= kNumSyrk16Tiles) ts = pick_syrk16_tile(nao);
+    p.T = kSyrk16Tiles[ts];
+    const int64_t nt = cdiv(nao, p.T);
+    p.ntl = nt * (nt + 1) / 2;
+    int64_t nsplit = cdiv(2048, p.ntl);
+    if (nsplit < cdiv(naux * p.ncp, kMaxSum16)) nsplit = cdiv(naux * p.ncp, kMaxSum16);
+    if (nsplit > naux) nsplit = naux;
+    p.pchunk = cdiv(naux, nsplit);
+    p.nsplit = cdiv(naux, p.pchunk);
+    p.Bdense = 2 * (size_t)naux * (size_t)(ldd * ldd);
+    p.Cw = 2 * (size_t)(p.ncp * ldd);
+    p.X = 2 * (size_t)(naux * nao * p.ncp);
+    p.kpart = sizeof(float) * (size_t)(p.nsplit * p.ntl) * p.T * p.T;
+    return p;
+}
+
+template <typename H>
+int make_dense_t(dfjk_ctx* h) {
+    const int64_t ldd = k16_ldd(h->nao);
+    int rc;
+    if ((rc = h->Bdense.ensure(k16_plan(h, 1).Bdense))) return rc;
+    const int64_t nt = cdiv(ldd, 64), ntile = nt * (nt + 1) / 2;
+    dense_copy<H><<<dim3((unsigned)ntile, (unsigned)h->naux), kT, 0, h->stream>>>(
+        static_cast<const H*>(h->B), h->ldB, h->nao, ldd, ntile, static_cast<H*>(h->Bdense.ptr));
+    DFJK_LAUNCH_CHECK("dense_copy");
+    h->dense_ready = true;
+    return DFJK_OK;
+}
+
 template <typename H>
 int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     const hipStream_t st = h->stream;
     const int64_t nao = h->nao, naux = h->naux;
-    const int64_t ldd = cdiv(nao, KC16) * KC16;  // dense row length: 64-deep chunks
-    const int64_t ncp = cdiv(ncol, KS) * KS;
+    const int64_t ldd = k16_ldd(nao);
+    const K16Plan plan = k16_plan(h, ncol);
+    const int64_t ncp = plan.ncp;
     int rc;
-    if (!h->dense_ready) {
-        if ((rc = h->Bdense.ensure(sizeof(H) * (size_t)naux * (size_t)(ldd * ldd)))) return rc;
-        const int64_t nt = cdiv(ldd, 64), ntile = nt * (nt + 1) / 2;
-        dense_copy<H><<<dim3((unsigned)ntile, (unsigned)naux), kT, 0, st>>>(
-            static_cast<const H*>(h->B), h->ldB, nao, ldd, ntile, static_cast<H*>(h->Bdense.ptr));
-        DFJK_LAUNCH_CHECK("dense_copy");
-        h->dense_ready = true;
-    }
-    if ((rc = h->Cw.ensure(sizeof(H) * (size_t)(ncp * ldd)))) return rc;
-    if ((rc = h->X.ensure(sizeof(H) * (size_t)(naux * nao * ncp)))) return rc;
+    if ((rc = h->Cw.ensure(plan.Cw)) || (rc = h->X.ensure(plan.X)) || (rc = h->kpart.ensure(plan.kpart)))
+        return rc;
+    if (!h->dense_ready && (rc = make_dense_t<H>(h))) return rc;
     H* Ct = static_cast<H*>(h->Cw.ptr);
     H* X = static_cast<H*>(h->X.ptr);
     const H* Bd = static_cast<const H*>(h->Bdense.ptr);
@@ -672,18 +710,7 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     launch_g16<H>(t, st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
-    int ts = h->k16_syrk_tile;
-    if (ts < 0 || ts >= kNumSyrk16Tiles) ts = pick_syrk16_tile(nao);
-    const int64_t T = kSyrk16Tiles[ts];
-    const int64_t nt = cdiv(nao, T), ntl = nt * (nt + 1) / 2;
-    // about 2048 workgroups, and no FP32 running sum longer than kMaxSum16
-    // terms (the split partials are added in FP64)
-    int64_t nsplit = cdiv(2048, ntl);
-    if (nsplit < cdiv(naux * ncp, kMaxSum16)) nsplit = cdiv(naux * ncp, kMaxSum16);
-    if (nsplit > naux) nsplit = naux;
-    const int64_t pchunk = cdiv(naux, nsplit);
-    nsplit = cdiv(naux, pchunk);
-    if ((rc = h->kpart.ensure(sizeof(float) * (size_t)(nsplit * ntl) * T * T))) return rc;
+    const int64_t T = plan.T, ntl = plan.ntl, nsplit = plan.nsplit, pchunk = plan.pchunk;
     float* part = static_cast<float*>(h->kpart.ptr);
     const dim3 grid((unsigned)(ntl * nsplit));
     h->prof.begin(PH_K_SYRK, st);
@@ -711,6 +738,30 @@ int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double*
     if (h->dtype == DFJK_F16) return k16_t<_Float16>(h, C, ncol, scale, K);
     set_error("16-bit exchange needs BF16 or FP16 B");
     return DFJK_E_DTYPE;
+}
+
+int k16_make_dense(dfjk_ctx* h) {
+    if (h->dtype == DFJK_BF16) return make_dense_t<uint16_t>(h);
+    if (h->dtype == DFJK_F16) return make_dense_t<_Float16>(h);
+    return DFJK_OK;
+}
+
+int k16_reserve(dfjk_ctx* h, int64_t max_ncol) {
+    // the SYRK tile may be changed later with dfjk_set_tile: reserve for both
+    const int keep = h->k16_syrk_tile;
+    size_t kp = 0;
+    K16Plan p{};
+    for (int t = 0; t < kNumSyrk16Tiles; ++t) {
+        h->k16_syrk_tile = t;
+        p = k16_plan(h, max_ncol);
+        if (p.kpart > kp) kp = p.kpart;
+    }
+    h->k16_syrk_tile = keep;
+    int rc;
+    if ((rc = h->Bdense.ensure(p.Bdense)) || (rc = h->Cw.ensure(p.Cw)) || (rc = h->X.ensure(p.X)) ||
+        (rc = h->kpart.ensure(kp)))
+        return rc;
+    return DFJK_OK;
 }
 
 int k16_tile_count() { return kNumG16Tiles; }

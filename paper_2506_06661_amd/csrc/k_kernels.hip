@@ -591,12 +591,26 @@ void syrk_splits(int64_t nrows, int64_t ntl, bool f32, int64_t* nsplit_out, int6
     *kchunk_out = kchunk;
 }
 
+// Workspace of one K build: X rows of nao elements and the GEMM2 split
+// partials (nrows contraction terms over ntl output tiles), in bytes.
+struct KBytes {
+    size_t X, kpart;
+};
+KBytes k_bytes(const dfjk_ctx* h, size_t elem, int64_t xrows, int64_t nrows, int64_t ntl) {
+    int64_t nsplit, kchunk;
+    syrk_splits(nrows, ntl, elem == 4, &nsplit, &kchunk);
+    return KBytes{elem * (size_t)xrows * (size_t)h->nao, elem * (size_t)(nsplit * ntl) * SY_T * SY_T};
+}
+
 template <typename T>
 int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, double scale, double* K) {
     const int64_t ldx = h->nao;
     const int64_t nrows = h->naux * ncol;
+    const int64_t nt = cdiv(h->nao, SY_T);
+    const int64_t ntl = nt * (nt + 1) / 2;
+    const KBytes need = k_bytes(h, sizeof(T), nrows, nrows, ntl);
     int rc;
-    if ((rc = h->X.ensure(sizeof(T) * (size_t)nrows * (size_t)ldx))) return rc;
+    if ((rc = h->X.ensure(need.X)) || (rc = h->kpart.ensure(need.kpart))) return rc;
     T* X = static_cast<T*>(h->X.ptr);
 
     h->prof.begin(PH_K, h->stream);
@@ -605,11 +619,8 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
     h->prof.end(PH_K_GEMM1, h->stream);
     if (rc) return rc;
 
-    const int64_t nt = cdiv(h->nao, SY_T);
-    const int64_t ntl = nt * (nt + 1) / 2;
     int64_t nsplit, kchunk;
     syrk_splits(nrows, ntl, sizeof(T) == 4, &nsplit, &kchunk);
-    if ((rc = h->kpart.ensure(sizeof(T) * (size_t)(nsplit * ntl) * SY_T * SY_T))) return rc;
     T* part = static_cast<T*>(h->kpart.ptr);
     h->prof.begin(PH_K_SYRK, h->stream);
     k_syrk<T><<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
@@ -633,8 +644,12 @@ template <typename T>
 int k_build_pair_t(dfjk_ctx* h, const void* L, const void* R, int64_t ncol, int sym, double scale, double* K) {
     const int64_t ldx = h->nao;
     const int64_t n1 = h->naux * ncol;  // rows of X_L (and of X_R)
+    const int64_t nt = cdiv(h->nao, SY_T);
+    const int64_t ntl = sym ? nt * (nt + 1) / 2 : nt * nt;
+    const int64_t nrows = sym ? 2 * n1 : n1;  // contraction length
+    const KBytes need = k_bytes(h, sizeof(T), 2 * n1, nrows, ntl);
     int rc;
-    if ((rc = h->X.ensure(sizeof(T) * (size_t)(2 * n1) * (size_t)ldx))) return rc;
+    if ((rc = h->X.ensure(need.X)) || (rc = h->kpart.ensure(need.kpart))) return rc;
     T* X = static_cast<T*>(h->X.ptr);
 
     h->prof.begin(PH_K, h->stream);
@@ -644,12 +659,8 @@ int k_build_pair_t(dfjk_ctx* h, const void* L, const void* R, int64_t ncol, int 
     h->prof.end(PH_K_GEMM1, h->stream);
     if (rc) return rc;
 
-    const int64_t nt = cdiv(h->nao, SY_T);
-    const int64_t ntl = sym ? nt * (nt + 1) / 2 : nt * nt;
-    const int64_t nrows = sym ? 2 * n1 : n1;  // contraction length
     int64_t nsplit, kchunk;
     syrk_splits(nrows, ntl, sizeof(T) == 4, &nsplit, &kchunk);
-    if ((rc = h->kpart.ensure(sizeof(T) * (size_t)(nsplit * ntl) * SY_T * SY_T))) return rc;
     T* part = static_cast<T*>(h->kpart.ptr);
     const dim3 grid((unsigned)(ntl * nsplit));
     h->prof.begin(PH_K_SYRK, h->stream);
@@ -798,6 +809,25 @@ int k_build_pair(dfjk_ctx* h, const double* L, const double* R, int64_t ncol, in
     return k_build_pair_t<float>(h, Lf, Rf, ncol, sym, scale, K);
 }
 
+
+int k_reserve(dfjk_ctx* h, int64_t max_ncol) {
+    const size_t elem = h->dtype == DFJK_F64 ? 8 : 4;
+    const int64_t nt = cdiv(h->nao, SY_T), lower = nt * (nt + 1) / 2;
+    const int64_t n1 = h->naux * max_ncol, half = h->naux * (max_ncol / 2);
+    // one factor of max_ncol columns; two factors of max_ncol / 2 each (the
+    // symmetric form contracts both over the lower tiles, the general one
+    // half of the rows over every tile)
+    const KBytes a = k_bytes(h, elem, n1, n1, lower);
+    const KBytes b = k_bytes(h, elem, 2 * half, 2 * half, lower);
+    const KBytes c = k_bytes(h, elem, 2 * half, half, nt * nt);
+    size_t kp = a.kpart > b.kpart ? a.kpart : b.kpart;
+    kp = kp > c.kpart ? kp : c.kpart;
+    int rc;
+    if ((rc = h->X.ensure(a.X > b.X ? a.X : b.X))) return rc;
+    if ((rc = h->kpart.ensure(kp))) return rc;
+    if (h->dtype != DFJK_F64 && (rc = h->Cw.ensure(sizeof(float) * (size_t)(h->nao * max_ncol)))) return rc;
+    return DFJK_OK;
+}
 
 int k_tile_count() { return kNumG1Tiles; }
 

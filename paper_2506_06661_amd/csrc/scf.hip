@@ -243,6 +243,11 @@ int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D) {
     return DFJK_OK;
 }
 
+int scf_reserve(dfjk_ctx* h) {
+    ScfWs ws;
+    return scf_ws(h, true, ws);
+}
+
 int scf_reset(dfjk_ctx* h) {
     h->scf_v_warm = false;
     h->scf_iter = 0;

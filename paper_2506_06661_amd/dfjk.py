@@ -47,7 +47,8 @@ class Mol(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("diis_space", ctypes.c_int), ("conv_tol", ctypes.c_double),
                 ("conv_tol_grad", ctypes.c_double), ("max_cycle", ctypes.c_int),
-                ("compensated_j", ctypes.c_int), ("k16", ctypes.c_int)]
+                ("compensated_j", ctypes.c_int), ("k16", ctypes.c_int), ("max_ncol", ctypes.c_int),
+                ("max_ndm", ctypes.c_int)]
 
 
 _lib = None
@@ -70,6 +71,8 @@ def lib():
         L.dfjk_build_K_factored.argtypes = [vp, vp, i64, vp, dbl, vp]
         L.dfjk_build_K_pair.argtypes = [vp, vp, vp, i64, i32, dbl, vp]
         L.dfjk_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.dfjk_update_B.argtypes = [vp]
+        L.dfjk_update_B.restype = i32
         L.dfjk_destroy.argtypes = [vp]
         L.dfjk_destroy.restype = None
         L.dfjk_last_error.restype = ctypes.c_char_p
@@ -195,6 +198,10 @@ def dfjk_build_K_factored(h, C, ncol: int, sign, scale: float, K) -> int:
 def dfjk_build_K_pair(h, L, R, ncol: int, sym: int, scale: float, K) -> int:
     return _check("dfjk_build_K_pair",
                   lib().dfjk_build_K_pair(h, _ptr(L), _ptr(R), ncol, sym, scale, _ptr(K)))
+
+
+def dfjk_update_B(h) -> int:
+    return _check("dfjk_update_B", lib().dfjk_update_B(h))
 
 
 def dfjk_workspace_bytes(h) -> int:
