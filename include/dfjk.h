@@ -124,6 +124,31 @@ int dfjk_init(dfjk_handle* h, const void* B_dev, int dtype, int64_t nao, int64_t
 int dfjk_build_J(dfjk_handle h, const double* D_dev, double* J_dev, double* rho_dev);
 
 /*
+ * dfjk_build_J without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, hosts that
+ * forbid hipMalloc.  Takes dfjk_init's arguments (B_dev, dtype, nao, naux,
+ * ldB, stream, opts; only opts->compensated_j is used, NULL = defaults) and
+ * dfjk_build_J's (D_dev, J_dev, rho_dev), and computes bitwise what a handle
+ * made with them would.  Its workspace is a fixed array of
+ * dfjk_static_scratch_bytes() bytes (128 MiB) in device memory that the
+ * library holds on each GPU it runs on until the process ends; sizes whose
+ * workspace does not fit are rejected with DFJK_E_INVALID before anything is
+ * enqueued.  The workspace is the packed density (3 npair doubles), naux x
+ * (a few) partial sums of rho and the pass-2 partials (npair doubles per row
+ * slice: about 4096 * 2048 / npair slices for FP64 B, more for reduced B):
+ * nao = 1024 with naux = 4096 and FP64 B needs 80 MB and fits; the same size
+ * with FP32 or 16-bit B, or nao = 2048, does not.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (two streams, two threads) race and
+ * give wrong results: serialise them.  Each call writes every workspace
+ * element it reads, so no clearing is needed between calls.  The device is
+ * the current one; its scratch address is looked up on the first call there.
+ * Asynchronous on `stream`.  Errors: as dfjk_init and dfjk_build_J.
+ */
+int dfjk_build_J_static(const void* B_dev, int dtype, int64_t nao, int64_t naux, int64_t ldB, void* stream,
+                        const dfjk_options* opts, const double* D_dev, double* J_dev, double* rho_dev);
+size_t dfjk_static_scratch_bytes(void);
+
+/*
  * The 3-index factor of Eq. eq:df:eri (Sec. IV.C.2): with the auxiliary
  * metric M = L L^T (Cholesky, lower L) and the 3-index integrals Q = (P|mu
  * nu), B = L^-1 Q.  No handle needed.

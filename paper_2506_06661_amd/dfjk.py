@@ -65,6 +65,10 @@ def lib():
         L.dfjk_init.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i64, i64, vp, ctypes.POINTER(Options)]
         L.dfjk_build_J.argtypes = [vp, vp, vp, vp]
         L.dfjk_build_J_diag.argtypes = [vp, vp, vp, vp, vp]
+        L.dfjk_build_J_static.argtypes = [vp, i32, i64, i64, i64, vp, ctypes.POINTER(Options), vp, vp, vp]
+        L.dfjk_build_J_static.restype = i32
+        L.dfjk_static_scratch_bytes.argtypes = []
+        L.dfjk_static_scratch_bytes.restype = ctypes.c_size_t
         L.dfjk_build_J_multi.argtypes = [vp, i64, vp, vp, vp]
         L.dfjk_form_B.argtypes = [i64, i64, vp, vp, i64, vp]
         L.dfjk_build_K.argtypes = [vp, vp, i64, vp, vp]
@@ -171,6 +175,18 @@ def dfjk_init(B, dtype: int, nao: int, naux: int, ldB: int, stream=None, opts: O
 
 def dfjk_build_J(h, D, J, rho=None) -> int:
     return _check("dfjk_build_J", lib().dfjk_build_J(h, _ptr(D), _ptr(J), _ptr(rho)))
+
+
+def dfjk_build_J_static(B, dtype: int, nao: int, naux: int, ldB: int, D, J, rho=None, stream=None,
+                        opts: Options | None = None) -> int:
+    """dfjk_build_J on the library's fixed scratch array (no device allocation)."""
+    return _check("dfjk_build_J_static", lib().dfjk_build_J_static(
+        _ptr(B), dtype, nao, naux, ldB, _stream(stream), ctypes.byref(opts) if opts else None, _ptr(D),
+        _ptr(J), _ptr(rho)))
+
+
+def dfjk_static_scratch_bytes() -> int:
+    return int(lib().dfjk_static_scratch_bytes())
 
 
 def dfjk_form_B(naux: int, ncol: int, M, Q, ldQ: int, stream=None) -> int:

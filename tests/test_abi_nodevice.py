@@ -108,3 +108,17 @@ def test_reserved_options_invalid(L):
     o.max_ncol, o.max_ndm = 2, 0
     assert L.dfjk_init(ctypes.byref(h), fake, 0, 4, 4, 10, None, ctypes.byref(o)) == -1
 
+
+def test_static_invalid_arguments(L):
+    import paper_2506_06661_amd as pkg
+    fake = ctypes.c_void_p(4096)
+    # dfjk_build_J_static checks its arguments before any device call
+    assert L.dfjk_build_J_static(None, 0, 4, 4, 10, None, None, fake, fake, None) == -1
+    assert L.dfjk_build_J_static(fake, 9, 4, 4, 10, None, None, fake, fake, None) == -1
+    assert L.dfjk_build_J_static(fake, 0, 4, 4, 9, None, None, fake, fake, None) == -1  # ldB < npair
+    assert "ldB" in pkg.dfjk_last_error()
+    assert L.dfjk_build_J_static(fake, 0, 4, 4, 10, None, None, None, fake, None) == -1
+    o = pkg.dfjk.default_options()
+    o.compensated_j = 7
+    assert L.dfjk_build_J_static(fake, 1, 4, 4, 10, None, ctypes.byref(o), fake, fake, None) == -1
+    assert L.dfjk_static_scratch_bytes() == 128 << 20
