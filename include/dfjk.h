@@ -225,7 +225,9 @@ enum { DFJK_SCF_C_VALID = 1 };
  * not be idempotent; Sec. IV.B: Pulay DIIS is the default accelerator):
  *   J, K of D (K through Cocc when flags has DFJK_SCF_C_VALID, else through
  *   the eigen-factors of D); F = H + J - K/2; E = tr(D(H+F))/2;
- *   e = FD - DF; DIIS over the last diis_space (F, e) pairs; aufbau on the
+ *   e = FD - DF; DIIS over the last diis_space (F, e) pairs (the oldest
+ *   dropped for good while the Gram matrix of the error vectors has a
+ *   condition number above 1e12); aufbau on the
  *   extrapolated F; D <- 2 C C^T, Cocc <- C (nao x nocc).
  *   H_dev    nao x nao FP64 core Hamiltonian (symmetric).
  *   D_dev    in: the density of this iteration; out: the next density.

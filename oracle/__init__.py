@@ -262,6 +262,28 @@ def aufbau(F: np.ndarray, nocc: int):
     return eps, C, 2.0 * C @ C.T
 
 
+DIIS_MAX_COND = 1e12
+
+
+def diis_prune(Fs, es, max_cond: float = DIIS_MAX_COND) -> int:
+    """Drop the oldest stored (F, e) pairs, in place, while the Gram matrix
+    <e_i, e_j> of the error vectors is worse conditioned than max_cond (2-norm
+    condition number; a singular Gram matrix counts as infinitely bad).  At
+    least one pair stays.  Returns the number dropped.  This is the reading
+    taken of the DIIS the paper names as default (Sec. IV.B), which it does
+    not detail: the usual safeguard against a near-singular subspace."""
+    dropped = 0
+    while len(es) > 1:
+        G = np.array([[float(np.sum(a * b)) for b in es] for a in es])
+        w = np.linalg.eigvalsh(G)
+        if w[0] > 0 and w[-1] / w[0] <= max_cond:
+            break
+        Fs.pop(0)
+        es.pop(0)
+        dropped += 1
+    return dropped
+
+
 def diis_extrapolate(Fs, es):
     """Pulay DIIS: minimise |sum_i c_i e_i| subject to sum_i c_i = 1 via the
     bordered system [[<e_i,e_j>, -1], [-1, 0]] [c; lam] = [0; -1]."""
@@ -324,6 +346,7 @@ def scf(B: np.ndarray, H: np.ndarray, nocc: int, dm0: np.ndarray | None = None,
             converged = True
             break
         E_prev = E
+        diis_prune(Fs, es)
         Fx, _ = diis_extrapolate(Fs, es)
         _, C, D = aufbau(Fx, nocc)
     return {"E": hist_E, "err": hist_err, "D": D, "C": C, "converged": converged,

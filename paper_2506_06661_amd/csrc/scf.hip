@@ -10,7 +10,8 @@
 //   e = F D - D F = G - G^T with G = F D (F, D symmetric);
 //   Pulay DIIS over the last `diis_space` (F, e): minimise |sum c_i e_i| with
 //   sum c_i = 1 through the bordered Gram system, solved by Gaussian
-//   elimination with partial pivoting; F' = sum c_i F_i;
+//   elimination with partial pivoting, after dropping the oldest pairs while
+//   the Gram matrix's condition number exceeds 1e12; F' = sum c_i F_i;
 //   aufbau on F' (Jacobi eigensolver): C = the nocc lowest eigenvectors,
 //   D_{k+1} = 2 C C^T.
 // Everything stays on the device; the host reads the iteration record only
@@ -58,21 +59,89 @@ __global__ void gram_update(double* __restrict__ gram, int space, int snew, Slot
     gram[sj * space + snew] = dotv[j];
 }
 
-// Bordered DIIS system for the m stored vectors in chronological order, solved
-// by Gaussian elimination with partial pivoting (one thread; m <= 15).
-__global__ void diis_solve(const double* __restrict__ gram, int space, Slots order, int m,
-                          double* __restrict__ coef) {
+constexpr double kDiisMaxCond = 1e12;
+
+// Extreme eigenvalues of a symmetric k x k matrix (k <= 15) by cyclic Jacobi
+// rotations (Golub & Van Loan, Sec. 8.5), on one thread.
+__device__ void small_eig_range(const double (*g)[16], int k, double* lo, double* hi) {
+    double a[16][16];
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) a[i][j] = g[i][j];
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                tot += a[i][j] * a[i][j];
+                if (i != j) off += a[i][j] * a[i][j];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < k - 1; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int r = 0; r < k; ++r) {  // columns p, q
+                    const double ap = a[r][p], aq = a[r][q];
+                    a[r][p] = c * ap - sn * aq;
+                    a[r][q] = sn * ap + c * aq;
+                }
+                for (int r = 0; r < k; ++r) {  // rows p, q
+                    const double ap = a[p][r], aq = a[q][r];
+                    a[p][r] = c * ap - sn * aq;
+                    a[q][r] = sn * ap + c * aq;
+                }
+            }
+    }
+    double l = a[0][0], h = a[0][0];
+    for (int i = 1; i < k; ++i) {
+        l = fmin(l, a[i][i]);
+        h = fmax(h, a[i][i]);
+    }
+    *lo = l;
+    *hi = h;
+}
+
+// Bordered DIIS system for the stored vectors in chronological order, solved
+// by Gaussian elimination with partial pivoting (one thread; m <= 15).  The
+// oldest vectors are dropped, for this and every later iteration, while the
+// Gram matrix of the remaining error vectors has a 2-norm condition number
+// above kDiisMaxCond (or is singular); at least the newest stays.  first[0]
+// holds the oldest iteration still in use (reset on iteration 1).  coef gets
+// m entries in the order of `order`, zero for dropped vectors.
+__global__ void diis_solve(const double* __restrict__ gram, int space, Slots order, int m, int iter,
+                          double* __restrict__ first, double* __restrict__ coef) {
     if (threadIdx.x != 0) return;
+    const int it0 = iter - m + 1;  // iteration of order.s[0]
+    int k0 = 0;                     // first index of order still kept
+    if (iter > 1) {
+        const int f = (int)first[0];
+        k0 = f > it0 ? f - it0 : 0;
+    }
+    if (k0 > m - 1) k0 = m - 1;
+    double g[16][16];
+    while (k0 < m - 1) {
+        const int k = m - k0;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) g[i][j] = gram[order.s[k0 + i] * space + order.s[k0 + j]];
+        double lo, hi;
+        small_eig_range(g, k, &lo, &hi);
+        if (lo > 0.0 && hi / lo <= kDiisMaxCond) break;
+        ++k0;
+    }
+    first[0] = (double)(it0 + k0);
+    for (int j = 0; j < k0; ++j) coef[j] = 0.0;
+    const int mk = m - k0;  // vectors kept: order.s[k0 .. m-1]
     double a[16][17];
-    const int n = m + 1;
-    for (int i = 0; i < m; ++i) {
-        for (int j = 0; j < m; ++j) a[i][j] = gram[order.s[i] * space + order.s[j]];
-        a[i][m] = -1.0;
+    const int n = mk + 1;
+    for (int i = 0; i < mk; ++i) {
+        for (int j = 0; j < mk; ++j) a[i][j] = gram[order.s[k0 + i] * space + order.s[k0 + j]];
+        a[i][mk] = -1.0;
         a[i][n] = 0.0;
     }
-    for (int j = 0; j < m; ++j) a[m][j] = -1.0;
-    a[m][m] = 0.0;
-    a[m][n] = -1.0;
+    for (int j = 0; j < mk; ++j) a[mk][j] = -1.0;
+    a[mk][mk] = 0.0;
+    a[mk][n] = -1.0;
     bool singular = false;
     for (int col = 0; col < n && !singular; ++col) {
         int piv = col;
@@ -100,9 +169,9 @@ __global__ void diis_solve(const double* __restrict__ gram, int space, Slots ord
             for (int c = r + 1; c < n; ++c) t -= a[r][c] * x[c];
             x[r] = t / a[r][r];
         }
-        for (int j = 0; j < m; ++j) coef[j] = x[j];
+        for (int j = 0; j < mk; ++j) coef[k0 + j] = x[j];
     } else {
-        for (int j = 0; j < m; ++j) coef[j] = j == m - 1 ? 1.0 : 0.0;
+        for (int j = 0; j < mk; ++j) coef[k0 + j] = j == mk - 1 ? 1.0 : 0.0;
     }
 }
 
@@ -150,7 +219,7 @@ struct ScfWs {
     int* iwork;
     double *J, *K, *F, *G, *Fx;            // SCF matrices
     double *Fh, *Eh;                       // DIIS history: space x n^2 each
-    double *gram, *coef, *dotv, *part, *en, *e_prev;
+    double *gram, *coef, *dotv, *part, *en, *e_prev, *diis_first;
     void* rec;
 };
 
@@ -166,13 +235,13 @@ static int scf_ws(dfjk_ctx* h, bool scf, ScfWs& ws) {
     const size_t oA = take(n2), oV = take(n2), ow = take(n), owork = take(n + 2), oCf = take(n2),
                  osign = take(n), oiw = take((n + 2 + 1) / 2);
     size_t oJ = 0, oK = 0, oF = 0, oG = 0, oFx = 0, oFh = 0, oEh = 0, ogr = 0, oco = 0, odv = 0,
-           opart = 0, oen = 0, oep = 0, orec = 0;
+           opart = 0, oen = 0, oep = 0, orec = 0, ofirst = 0;
     if (scf) {
         oJ = take(n2), oK = take(n2), oF = take(n2), oG = take(n2), oFx = take(n2);
         oFh = take((size_t)space * n2), oEh = take((size_t)space * n2);
         ogr = take((size_t)space * space), oco = take(16), odv = take(16),
         opart = take(dots_part_elems(kMaxDots)), oen = take(16), oep = take(1),
-        orec = take(sizeof(ScfRecord) / sizeof(double) + 1);
+        orec = take(sizeof(ScfRecord) / sizeof(double) + 1), ofirst = take(1);
     }
     if (need * sizeof(double) > h->eig.bytes) h->scf_v_warm = false;  // fresh buffer
     int rc = h->eig.ensure(need * sizeof(double));
@@ -200,6 +269,7 @@ static int scf_ws(dfjk_ctx* h, bool scf, ScfWs& ws) {
         ws.en = base + oen;
         ws.e_prev = base + oep;
         ws.rec = base + orec;
+        ws.diis_first = base + ofirst;
     }
     return DFJK_OK;
 }
@@ -309,7 +379,7 @@ int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, i
     scf_record<<<1, 64, 0, st>>>(ws.en, ws.gram, space, snew, iter, h->opts.conv_tol,
                                  h->opts.conv_tol_grad, ws.e_prev, static_cast<ScfRecord*>(ws.rec));
     DFJK_LAUNCH_CHECK("scf_record");
-    diis_solve<<<1, 64, 0, st>>>(ws.gram, space, order, m, ws.coef);
+    diis_solve<<<1, 64, 0, st>>>(ws.gram, space, order, m, iter, ws.diis_first, ws.coef);
     DFJK_LAUNCH_CHECK("diis_solve");
     {
         FList fl{};

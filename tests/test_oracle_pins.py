@@ -349,6 +349,38 @@ def test_diis_coefficients_sum_to_one():
     assert np.allclose(c, c_ls, atol=1e-10)
 
 
+def test_diis_prune_drops_oldest_when_ill_conditioned():
+    """A repeated error vector makes the Gram matrix singular: the oldest
+    pair goes, and the extrapolation over the two left equals the closed form
+    of two-vector DIIS, c_1 = <e_2, e_2 - e_1> / |e_1 - e_2|^2, c_2 = 1 - c_1."""
+    rng = np.random.default_rng(9)
+    e1, e2 = rng.standard_normal((5, 5)), rng.standard_normal((5, 5))
+    F0, F1, F2 = (rng.standard_normal((5, 5)) for _ in range(3))
+    Fs, es = [F0, F1, F2], [e1.copy(), e1.copy(), e2]
+    assert oracle.diis_prune(Fs, es) == 1
+    assert Fs[0] is F1 and len(es) == 2
+    Fx, c = oracle.diis_extrapolate(Fs, es)
+    d = e1 - e2
+    c1 = float(np.sum(e2 * (e2 - e1))) / float(np.sum(d * d))
+    assert np.allclose(c, [c1, 1 - c1], atol=1e-12)
+    assert np.allclose(Fx, c1 * F1 + (1 - c1) * F2, atol=1e-12)
+
+
+def test_diis_prune_threshold():
+    """Orthogonal error vectors of norms 1e7 and 1 (Gram condition 1e14)
+    lose the older; norms 1e5 and 1 (1e10) keep both; one vector stays."""
+    e_a = np.zeros((3, 3))
+    e_a[0, 1] = 1.0
+    e_b = np.zeros((3, 3))
+    e_b[2, 0] = 1.0
+    Fs, es = [np.eye(3), 2 * np.eye(3)], [1e7 * e_a, e_b]
+    assert oracle.diis_prune(Fs, es) == 1 and len(es) == 1 and es[0] is e_b
+    Fs, es = [np.eye(3), 2 * np.eye(3)], [1e5 * e_a, e_b]
+    assert oracle.diis_prune(Fs, es) == 0 and len(es) == 2
+    Fs, es = [np.eye(3)], [np.zeros((3, 3))]
+    assert oracle.diis_prune(Fs, es) == 0 and len(es) == 1
+
+
 @pytest.mark.slow
 def test_scf_converged_state():
     """At convergence: FD - DF ~ 0, D^2 = 2D, tr D = 2 nocc, and D is built
