@@ -77,7 +77,8 @@ typedef struct {
                              1 = compensated FP32 (Dot2), 0 = plain FP32 */
     int k16;              /* BF16/FP16 B, exchange from C: 1 = 16-bit matrix cores
                              (the handle keeps a dense 16-bit copy of B, naux *
-                             ceil64(nao)^2 elements, made in dfjk_init when
+                             ceil64(nao) * (ceil64(nao) + 64) elements, made in
+                             dfjk_init when
                              max_ncol > 0, else on the first K call; K then
                              uses B's contents as they were when the copy was
                              made: call dfjk_update_B after changing them; C

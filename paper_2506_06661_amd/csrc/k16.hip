@@ -6,8 +6,8 @@
 // result row 4(l/16)+r, column l%16 in FP32).  The packed triangle is
 // contiguous along the contraction index only below the diagonal, so the
 // handle keeps a dense 16-bit copy of every B_P (both triangles, row length
-// padded to a multiple of 32 with zeros), made once with an LDS-tiled
-// transpose.  Then
+// padded to a multiple of 64 with zeros, rows ldd + 64 elements apart), made
+// once with an LDS-tiled transpose.  Then
 //   GEMM1: X[P][mu][i] = sum_nu Bd_P[mu][nu] Ct[i][nu]   (Ct = C^T in 16 bits)
 //   GEMM2: K[mu][nu]   = 2 sum_{P,i} X[P][mu][i] X[P][nu][i]
 // with X stored in 16 bits, rows (P, mu) of ncp (nocc padded to 32) entries,
@@ -68,7 +68,7 @@ struct Mma16<_Float16> {
 // outside the triangle or the matrix become zero, so the pad is zero too.
 template <typename H>
 __global__ __launch_bounds__(kT) void dense_copy(const H* __restrict__ B, int64_t ldB, int64_t nao,
-                                                  int64_t ldd, int64_t ntile, H* __restrict__ Bd) {
+                                                  int64_t ldd, int64_t rs, int64_t ntile, H* __restrict__ Bd) {
     __shared__ H tile[64][65];
     const int64_t P = blockIdx.y;
     const int64_t t = blockIdx.x;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kT) void dense_copy(const H* __restrict__ B, int64_
     const int64_t J = t - I * (I + 1) / 2;
     const int64_t nu0 = I * 64, mu0 = J * 64;
     const H* Bp = B + P * ldB;
-    H* D = Bd + P * ldd * ldd;
+    H* D = Bd + P * ldd * rs;
     for (int e = threadIdx.x; e < 64 * 64; e += kT) {
         const int a = e / 64, b = e % 64;  // row nu0+a, column mu0+b
         const int64_t nu = nu0 + a, mu = mu0 + b;
@@ -90,10 +90,10 @@ __global__ __launch_bounds__(kT) void dense_copy(const H* __restrict__ B, int64_
     for (int e = threadIdx.x; e < 64 * 64; e += kT) {
         const int a = e / 64, b = e % 64;
         const int64_t nu = nu0 + a, mu = mu0 + b;
-        if (nu < ldd && mu < ldd && mu <= nu) D[nu * ldd + mu] = tile[a][b];  // lower half
+        if (nu < ldd && mu < ldd && mu <= nu) D[nu * rs + mu] = tile[a][b];  // lower half
         // transposed: row mu0+a, column nu0+b holds B[nu0+b][mu0+a]
         const int64_t r = mu0 + a, c = nu0 + b;
-        if (r < ldd && c < ldd && r < c) D[r * ldd + c] = tile[b][a];
+        if (r < ldd && c < ldd && r < c) D[r * rs + c] = tile[b][a];
     }
     (void)ntile;
 }
@@ -102,12 +102,12 @@ __global__ __launch_bounds__(kT) void dense_copy(const H* __restrict__ B, int64_
 // nu < ldd (zero outside C)
 template <typename H>
 __global__ void c_transpose(const double* __restrict__ C, int64_t nao, int64_t ncol, int64_t ncp,
-                            int64_t ldd, H* __restrict__ Ct) {
+                            int64_t ldd, int64_t rs, H* __restrict__ Ct) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncp * ldd) return;
     const int64_t i = e / ldd, nu = e % ldd;
     const double v = (i < ncol && nu < nao) ? C[nu * ncol + i] : 0.0;
-    Ct[e] = Mma16<H>::from_double(v);
+    Ct[i * rs + nu] = Mma16<H>::from_double(v);
 }
 
 // ---------------------------------------------------------------- GEMM1
@@ -131,7 +131,7 @@ struct G16Stage {
 };
 
 template <typename H, int NI>
-__device__ inline void g16_load(G16Stage<H, NI>& st, const H* __restrict__ A, int64_t ldd,
+__device__ inline void g16_load(G16Stage<H, NI>& st, const H* __restrict__ A, int64_t ldd, int64_t rs,
                                 const H* __restrict__ Ct, int64_t ncp, int64_t mu0, int64_t i0,
                                 int64_t k0, int tid) {
     constexpr int NA = 128 * KC16 / 8, NB = 16 * NI * KC16 / 8;
@@ -141,7 +141,7 @@ __device__ inline void g16_load(G16Stage<H, NI>& st, const H* __restrict__ A, in
         const int r = e >> 3, q = e & 7;
         const int64_t mu = mu0 + r;
         st.a[j] = (e < NA && mu < ldd && k0 + 8 * q < ldd)
-                      ? *reinterpret_cast<const u4*>(A + mu * ldd + k0 + 8 * q)
+                      ? *reinterpret_cast<const u4*>(A + mu * rs + k0 + 8 * q)
                       : u4{0u, 0u, 0u, 0u};
     }
 #pragma unroll
@@ -150,7 +150,7 @@ __device__ inline void g16_load(G16Stage<H, NI>& st, const H* __restrict__ A, in
         const int r = e >> 3, q = e & 7;
         const int64_t i = i0 + r;
         st.b[j] = (e < NB && i < ncp && k0 + 8 * q < ldd)
-                      ? *reinterpret_cast<const u4*>(Ct + i * ldd + k0 + 8 * q)
+                      ? *reinterpret_cast<const u4*>(Ct + i * rs + k0 + 8 * q)
                       : u4{0u, 0u, 0u, 0u};
     }
 }
@@ -177,7 +177,7 @@ __device__ inline int64_t xcd_lid(int64_t hw, int64_t nblk) {
 }
 
 template <typename H, int NI>
-__global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ldd, int64_t nao,
+__global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ldd, int64_t rs, int64_t nao,
                                              const H* __restrict__ Ct, int64_t ncol, int64_t ncp,
                                              H* __restrict__ X, int64_t nib, int64_t nmb, int64_t nblk) {
     constexpr int BI = 16 * NI, BM = 128;
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ld
     const int64_t lid = xcd_lid(blockIdx.x, nblk);
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, mu0 = mb * BM;
-    const H* A = Bd + P * ldd * ldd;
+    const H* A = Bd + P * ldd * rs;
     v4f acc[2][NI];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -195,13 +195,13 @@ __global__ __launch_bounds__(kT) void g1_16(const H* __restrict__ Bd, int64_t ld
         for (int b = 0; b < NI; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     const int64_t nk = ldd / KC16 + (ldd % KC16 ? 1 : 0);
     G16Stage<H, NI> st;
-    g16_load<H, NI>(st, A, ldd, Ct, ncp, mu0, i0, 0, tid);
+    g16_load<H, NI>(st, A, ldd, rs, Ct, ncp, mu0, i0, 0, tid);
     g16_store<H, NI>(st, sA[0], sB[0], tid);
     __syncthreads();
     for (int64_t kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
         const bool more = kc + 1 < nk;
-        if (more) g16_load<H, NI>(st, A, ldd, Ct, ncp, mu0, i0, (kc + 1) * KC16, tid);
+        if (more) g16_load<H, NI>(st, A, ldd, rs, Ct, ncp, mu0, i0, (kc + 1) * KC16, tid);
 #pragma unroll
         for (int ks = 0; ks < KC16 / KS; ++ks) {
             u4 a[2];
@@ -247,7 +247,7 @@ struct G16BStage {
 };
 
 template <typename H, int NI>
-__device__ inline void g16d_load_b(G16BStage<NI>& st, const H* __restrict__ Ct, int64_t ldd, int64_t ncp,
+__device__ inline void g16d_load_b(G16BStage<NI>& st, const H* __restrict__ Ct, int64_t ldd, int64_t rs, int64_t ncp,
                                    int64_t i0, int64_t k0, int tid) {
     constexpr int NB = 16 * NI * KC16 / 8;
 #pragma unroll
@@ -256,7 +256,7 @@ __device__ inline void g16d_load_b(G16BStage<NI>& st, const H* __restrict__ Ct, 
         const int r = e >> 3, q = e & 7;
         const int64_t i = i0 + r;
         st.b[j] = (e < NB && i < ncp && k0 + 8 * q < ldd)
-                      ? *reinterpret_cast<const u4*>(Ct + i * ldd + k0 + 8 * q)
+                      ? *reinterpret_cast<const u4*>(Ct + i * rs + k0 + 8 * q)
                       : u4{0u, 0u, 0u, 0u};
     }
 }
@@ -272,7 +272,7 @@ __device__ inline void g16d_store_b(const G16BStage<NI>& st, H (*sB)[LROW64], in
 }
 
 template <typename H, int TM>
-__device__ inline void g16d_load_a(u4 (&fa)[TM][KC16 / KS], const H* __restrict__ A, int64_t ldd,
+__device__ inline void g16d_load_a(u4 (&fa)[TM][KC16 / KS], const H* __restrict__ A, int64_t ldd, int64_t rs,
                                    int64_t row0, int64_t k0, int lane) {
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
@@ -280,14 +280,14 @@ __device__ inline void g16d_load_a(u4 (&fa)[TM][KC16 / KS], const H* __restrict_
 #pragma unroll
         for (int ks = 0; ks < KC16 / KS; ++ks) {
             const int64_t k = k0 + ks * KS + 8 * (lane >> 4);
-            fa[t][ks] = (row < ldd && k < ldd) ? *reinterpret_cast<const u4*>(A + row * ldd + k)
+            fa[t][ks] = (row < ldd && k < ldd) ? *reinterpret_cast<const u4*>(A + row * rs + k)
                                                : u4{0u, 0u, 0u, 0u};
         }
     }
 }
 
 template <typename H, int TM, int NI>
-__global__ __launch_bounds__(kT) void g1_16d(const H* __restrict__ Bd, int64_t ldd, int64_t nao,
+__global__ __launch_bounds__(kT) void g1_16d(const H* __restrict__ Bd, int64_t ldd, int64_t rs, int64_t nao,
                                               const H* __restrict__ Ct, int64_t ncol, int64_t ncp,
                                               H* __restrict__ X, int64_t nib, int64_t nmb, int64_t nblk) {
     constexpr int BI = 16 * NI, BM = 64 * TM, NKS = KC16 / KS;
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kT) void g1_16d(const H* __restrict__ Bd, int64_t l
     const int64_t lid = xcd_lid(blockIdx.x, nblk);
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
     const int64_t i0 = ib * BI, row0 = mb * BM + wave * 16 * TM;
-    const H* A = Bd + P * ldd * ldd;
+    const H* A = Bd + P * ldd * rs;
     v4f acc[TM][NI];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
@@ -305,16 +305,16 @@ __global__ __launch_bounds__(kT) void g1_16d(const H* __restrict__ Bd, int64_t l
     const int64_t nk = ldd / KC16 + (ldd % KC16 ? 1 : 0);
     u4 fa[TM][NKS], fn[TM][NKS];
     G16BStage<NI> st;
-    g16d_load_a<H, TM>(fa, A, ldd, row0, 0, lane);
-    g16d_load_b<H, NI>(st, Ct, ldd, ncp, i0, 0, tid);
+    g16d_load_a<H, TM>(fa, A, ldd, rs, row0, 0, lane);
+    g16d_load_b<H, NI>(st, Ct, ldd, rs, ncp, i0, 0, tid);
     g16d_store_b<H, NI>(st, sB[0], tid);
     __syncthreads();
     for (int64_t kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
         const bool more = kc + 1 < nk;
         if (more) {
-            g16d_load_a<H, TM>(fn, A, ldd, row0, (kc + 1) * KC16, lane);
-            g16d_load_b<H, NI>(st, Ct, ldd, ncp, i0, (kc + 1) * KC16, tid);
+            g16d_load_a<H, TM>(fn, A, ldd, rs, row0, (kc + 1) * KC16, lane);
+            g16d_load_b<H, NI>(st, Ct, ldd, rs, ncp, i0, (kc + 1) * KC16, tid);
         }
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
@@ -543,6 +543,316 @@ __global__ __launch_bounds__(kT, 1) void syrk_16w(const H* __restrict__ X, int64
             }
 }
 
+// ---------------------------------------------------------------- 32 x 32 forms
+// v_mfma_f32_32x32x16_{bf16,f16}: lane l supplies A[l%32][8(l/32)+j] and
+// B[8(l/32)+j][l%32] (j < 8, one 16-byte piece each); result register r of
+// lane l is row 8(r/4) + 4(l/32) + r%4, column l%32.  Twice the work of a
+// 16 x 16 x 32 step per operand piece, and on MI355X the register-only rate
+// of this shape sustains 0.96-0.98 of the published peak against 0.87 for
+// the 16 x 16 one (measured).
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+template <typename H>
+struct Mma32;
+template <>
+struct Mma32<uint16_t> {
+    __device__ static v16f step(u4 a, u4 b, v16f c) {
+        v8bf av, bv;
+        __builtin_memcpy(&av, &a, 16);
+        __builtin_memcpy(&bv, &b, 16);
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mma32<_Float16> {
+    __device__ static v16f step(u4 a, u4 b, v16f c) {
+        v8h av, bv;
+        __builtin_memcpy(&av, &a, 16);
+        __builtin_memcpy(&bv, &b, 16);
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, c, 0, 0, 0);
+    }
+};
+__device__ inline int mrow32(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+__device__ inline v16f zero16() {
+    v16f z;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = 0.f;
+    return z;
+}
+
+// 64-byte rows for 32 x 32 operand reads: piece p of row r at p ^ f(r), f
+// from bits 2 and 4 of the row, free of bank conflicts when lanes l and
+// l + 16 (l < 8) are served together and read rows 16 apart at one piece.
+__device__ inline int swz4c(int row, int piece) {
+    const int f = ((row >> 2) & 1) | (((row >> 4) & 1) << 1);
+    return (piece ^ f) * 8;
+}
+// Staging order of those panels: thread t stores piece t & 3 of row
+// st_row(t), so that lanes l and l + 16 store rows whose r % 4 differ (lane
+// bit 4 becomes row bit 1).  Measured on MI355X (SQ_LDS_BANK_CONFLICT): the
+// swz4 layout with rows t >> 2 spent 37.5% of LDS cycles in conflicts with
+// 32 x 32 operand reads, this one none.
+__device__ inline int st_row(int t) {
+    return ((t >> 2) & 1) | (((t >> 4) & 1) << 1) | (((t >> 3) & 1) << 2) | ((t >> 5) << 3);
+}
+
+// GEMM1, X[P][mu][i] = sum_nu Bd_P[mu][nu] Ct[i][nu], wide form: workgroup =
+// 8 wavefronts, 4 along mu (32 rows each) x 2 along i (16*NI columns each),
+// i.e. a 128 x 32*NI output tile per P; with 32*NI >= the padded orbital
+// count every element of Bd_P is read from memory once.  Per 64-deep chunk
+// the 128 rows of Bd_P and the 32*NI rows of Ct are staged in LDS (128-byte
+// rows, piece p of row r at p ^ (r & 7)), double-buffered, the next chunk
+// loaded into registers while the current one is multiplied on
+// 16 x 16 x 32 steps (2 x NI result blocks per wavefront).
+constexpr int kT8 = 512;
+constexpr int GW_M = 128;
+
+template <int NI>
+struct GwStage {
+    static constexpr int NP = (GW_M + 32 * NI) * 8;        // 16-byte pieces per chunk
+    static constexpr int PER = (NP + kT8 - 1) / kT8;       // per thread
+    u4 v[PER];
+};
+
+template <typename H, int NI, bool PRE, bool SCHED = false>
+__global__ __launch_bounds__(kT8, 1) void g1_w(const H* __restrict__ Bd, int64_t ldd, int64_t rs, int64_t nao,
+                                                const H* __restrict__ Ct, int64_t ncol, int64_t ncp,
+                                                H* __restrict__ X, int64_t nib, int64_t nmb, int64_t nblk) {
+    constexpr int BI = 32 * NI, ROWS = GW_M + BI;
+    __shared__ uint16_t sT[2][ROWS][LROW64];  // rows 0..127: Bd_P; rows 128..: Ct
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 3, wn = wave >> 2;
+    const int64_t lid = xcd_lid(blockIdx.x, nblk);
+    const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
+    const int64_t i0 = ib * BI, mu0 = mb * GW_M;
+    const uint16_t* A = reinterpret_cast<const uint16_t*>(Bd) + P * ldd * rs;
+    const uint16_t* Bt = reinterpret_cast<const uint16_t*>(Ct);
+    using St = GwStage<NI>;
+    // piece e = tid + j*512: row e>>3, piece e&7 of the 64-deep chunk
+    const uint16_t* src[St::PER];
+    bool ok[St::PER];
+#pragma unroll
+    for (int j = 0; j < St::PER; ++j) {
+        const int e = tid + j * kT8, r = e >> 3;
+        if (r < GW_M) {
+            const int64_t row = mu0 + r;
+            ok[j] = e < St::NP && row < ldd;
+            src[j] = A + (ok[j] ? row : 0) * rs + 8 * (e & 7);
+        } else {
+            const int64_t row = i0 + (r - GW_M);
+            ok[j] = e < St::NP && row < ncp;
+            src[j] = Bt + (ok[j] ? row : 0) * rs + 8 * (e & 7);
+        }
+    }
+    const u4 z4 = u4{0u, 0u, 0u, 0u};
+    St st;
+    // loads always read a valid address (row 0 stands in for rows outside the
+    // operands); the pieces of such rows are replaced by zeros when stored
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < St::PER; ++j) st.v[j] = *reinterpret_cast<const u4*>(src[j] + k0);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < St::PER; ++j) {
+            const int e = tid + j * kT8;
+            if (e < St::NP) *reinterpret_cast<u4*>(&sT[buf][e >> 3][swz(e >> 3, e & 7)]) = ok[j] ? st.v[j] : z4;
+        }
+    };
+    v4f acc[2][NI];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t nk = ldd / KC16;  // ldd is a multiple of 64
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nk;
+        if (more) load((kc + 1) * KC16);
+#pragma unroll
+        for (int ks = 0; ks < KC16 / KS; ++ks) {
+            const int pc = ks * (KS / 8) + (lane >> 4);
+            u4 a[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int r = wm * 32 + t * 16 + (lane & 15);
+                a[t] = *reinterpret_cast<const u4*>(&sT[buf][r][swz(r, pc)]);
+            }
+            if constexpr (PRE) {
+                // every operand piece of the step is requested before the first
+                // product, so the LDS latency is paid once per step
+                u4 b[NI];
+#pragma unroll
+                for (int n = 0; n < NI; ++n) {
+                    const int r = GW_M + wn * 16 * NI + n * 16 + (lane & 15);
+                    b[n] = *reinterpret_cast<const u4*>(&sT[buf][r][swz(r, pc)]);
+                }
+#pragma unroll
+                for (int n = 0; n < NI; ++n)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) acc[t][n] = Mma16<H>::step(a[t], b[n], acc[t][n]);
+                if constexpr (SCHED) {
+                    // keep several operand reads in flight ahead of the products:
+                    // 6 reads, then (2 products, 1 read) until the reads run out
+                    constexpr int R0 = 6 < NI + 2 ? 6 : NI + 2;
+                    __builtin_amdgcn_sched_group_barrier(0x100, R0, 0);
+#pragma unroll
+                    for (int g = 0; g < NI + 2 - R0; ++g) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
+                    __builtin_amdgcn_sched_group_barrier(0x008, 2 * NI - 2 * (NI + 2 - R0), 0);
+                }
+            } else {
+#pragma unroll
+                for (int n = 0; n < NI; ++n) {
+                    const int r = GW_M + wn * 16 * NI + n * 16 + (lane & 15);
+                    const u4 b = *reinterpret_cast<const u4*>(&sT[buf][r][swz(r, pc)]);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) acc[t][n] = Mma16<H>::step(a[t], b, acc[t][n]);
+                }
+            }
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int n = 0; n < NI; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t mu = mu0 + wm * 32 + t * 16 + 4 * (lane >> 4) + r;
+                const int64_t i = i0 + wn * 16 * NI + n * 16 + (lane & 15);
+                if (mu < nao && i < ncp)
+                    X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[t][n][r] : 0.f);
+            }
+}
+
+// GEMM2 on 256 x 256 lower tiles of K with 8 wavefronts (4 along mu x 2
+// along nu, 64 x 128 each = 2 x 4 result blocks of 32 x 32 on 32 x 32 x 16
+// steps).  The contraction over (P, i) runs in 32-wide steps inside each P;
+// two steps (possibly of consecutive P) are staged per barrier, both
+// 256-row panels of each in LDS, double-buffered, the next pair prefetched
+// into registers.  Rows past nao read row nao-1: they only feed output rows
+// and columns past nao, which the finish discards.
+constexpr int kSyNS = 2;  // 32-wide steps per barrier
+
+template <typename H>
+__global__ __launch_bounds__(kT8, 1) void syrk_32(const H* __restrict__ X, int64_t nao, int64_t ncp,
+                                                   int64_t naux, int64_t pchunk, int64_t ntl, int64_t nblk,
+                                                   float* __restrict__ part) {
+    __shared__ uint16_t sA[2][kSyNS][256][LROW];
+    __shared__ uint16_t sB[2][kSyNS][256][LROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t lid = xcd_lid(blockIdx.x, nblk);
+    const int64_t t = lid % ntl, s = lid / ntl;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int64_t J = t - I * (I + 1) / 2;
+    const int64_t mu0 = I * 256, nu0 = J * 256;
+    const int64_t P0 = s * pchunk, P1 = P0 + pchunk < naux ? P0 + pchunk : naux;
+    v16f acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = zero16();
+    // staging: each panel of one step is 256 rows x 4 pieces = 1024 pieces, 2 per thread
+    int64_t roff_a[2], roff_b[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int64_t r = st_row(tid) + 128 * j;
+        roff_a[j] = (mu0 + r < nao ? mu0 + r : nao - 1) * ncp + 8 * (tid & 3);
+        roff_b[j] = (nu0 + r < nao ? nu0 + r : nao - 1) * ncp + 8 * (tid & 3);
+    }
+    const int64_t nks = ncp / KS;
+    const int64_t nsteps = (P1 > P0 ? P1 - P0 : 0) * nks;  // (P, 32-wide step) in order
+    const int64_t nchunks = (nsteps + kSyNS - 1) / kSyNS;
+    if (nchunks > 0) {
+        u4 sta[kSyNS][2], stb[kSyNS][2];
+        const uint16_t* Pb = reinterpret_cast<const uint16_t*>(X) + P0 * nao * ncp;
+        int64_t kk = 0, left = nsteps;
+        const u4 z4 = u4{0u, 0u, 0u, 0u};
+        auto load = [&]() {
+#pragma unroll
+            for (int q = 0; q < kSyNS; ++q) {
+                const bool live = left > 0;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    sta[q][j] = live ? *reinterpret_cast<const u4*>(Pb + kk + roff_a[j]) : z4;
+                    stb[q][j] = live ? *reinterpret_cast<const u4*>(Pb + kk + roff_b[j]) : z4;
+                }
+                if (live) {
+                    --left;
+                    kk += KS;
+                    if (kk == ncp) {
+                        kk = 0;
+                        Pb += nao * ncp;
+                    }
+                }
+            }
+        };
+        auto store = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < kSyNS; ++q)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r = st_row(tid) + 128 * j, p = tid & 3;
+                    *reinterpret_cast<u4*>(&sA[buf][q][r][swz4c(r, p)]) = sta[q][j];
+                    *reinterpret_cast<u4*>(&sB[buf][q][r][swz4c(r, p)]) = stb[q][j];
+                }
+        };
+        load();
+        store(0);
+        __syncthreads();
+        for (int64_t c = 0; c < nchunks; ++c) {
+            const int buf = c & 1;
+            const bool more = c + 1 < nchunks;
+            if (more) load();
+#pragma unroll
+            for (int q = 0; q < kSyNS; ++q)
+#pragma unroll
+                for (int ks = 0; ks < KS / 16; ++ks) {
+                    const int pc = 2 * ks + (lane >> 5);
+                    u4 a[2], b[4];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int r = wm * 64 + u * 32 + (lane & 31);
+                        a[u] = *reinterpret_cast<const u4*>(&sA[buf][q][r][swz4c(r, pc)]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int r = wn * 128 + u * 32 + (lane & 31);
+                        b[u] = *reinterpret_cast<const u4*>(&sB[buf][q][r][swz4c(r, pc)]);
+                    }
+#pragma unroll
+                    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                        for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = Mma32<H>::step(a[ti], b[tj], acc[ti][tj]);
+                }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    float* out = part + (s * ntl + t) * (int64_t)(256 * 256);
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = wm * 64 + ti * 32 + mrow32(lane, r);
+                const int n = wn * 128 + tj * 32 + (lane & 31);
+                out[m * 256 + n] = acc[ti][tj][r];
+            }
+}
+
 // K = scale * sum_s part[s][t] over the lower triangle, mirrored (diagonal
 // tiles use m >= n only, so K is exactly symmetric).
 // grid: kFin16 blocks per lower tile, each adding up a contiguous slice of it
@@ -575,19 +885,27 @@ __global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ pa
 }
 
 template <typename H, int NI>
-void launch_g1(hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
+void launch_g1(hipStream_t st, const H* Bd, int64_t ldd, int64_t rs, int64_t nao, const H* Ct, int64_t ncol,
                int64_t ncp, H* X, int64_t naux) {
     const int64_t nib = cdiv(ncp, 16 * NI), nmb = cdiv(nao, 128);
     const int64_t nblk = nib * nmb * naux;
-    g1_16<H, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
+    g1_16<H, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, rs, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
 }
 
 template <typename H, int TM, int NI>
-void launch_g1d(hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
+void launch_g1d(hipStream_t st, const H* Bd, int64_t ldd, int64_t rs, int64_t nao, const H* Ct, int64_t ncol,
                 int64_t ncp, H* X, int64_t naux) {
     const int64_t nib = cdiv(ncp, 16 * NI), nmb = cdiv(nao, 64 * TM);
     const int64_t nblk = nib * nmb * naux;
-    g1_16d<H, TM, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
+    g1_16d<H, TM, NI><<<dim3((unsigned)nblk), kT, 0, st>>>(Bd, ldd, rs, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
+}
+
+template <typename H, int NI, bool PRE = true, bool SCHED = false>
+void launch_gw(hipStream_t st, const H* Bd, int64_t ldd, int64_t rs, int64_t nao, const H* Ct, int64_t ncol,
+               int64_t ncp, H* X, int64_t naux) {
+    const int64_t nib = cdiv(ncp, 32 * NI), nmb = cdiv(nao, GW_M);
+    const int64_t nblk = nib * nmb * naux;
+    g1_w<H, NI, PRE, SCHED><<<dim3((unsigned)nblk), kT8, 0, st>>>(Bd, ldd, rs, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
 }
 
 // Compiled 16-bit GEMM1 tiles: (orbital columns, basis-function rows) per
@@ -599,14 +917,30 @@ struct G16Tile {
     int cols, rows;
 };
 constexpr G16Tile kG16Tiles[] = {{64, 128}, {128, 128}, {208, 128}, {128, 128}, {208, 128},
-                                 {128, 256}, {64, 256}};
+                                 {128, 256}, {64, 256}, {416, 128}};
+// 7: g1_w, 8 wavefronts, both operands staged in LDS, 416 columns, operand
+// reads scheduled ahead of the products
 constexpr int kNumG16Tiles = sizeof(kG16Tiles) / sizeof(kG16Tiles[0]);
 
 // Default tile: least padded orbital columns per unit of measured rate.  On
 // MI355X at nao=2048, naux=1024, nocc=400 (BF16) the tiles of 64, 128 and 208
 // columns (indices 0, 1, 4) executed 468, 740 and 741 TFLOP/s counting the
 // padded columns (435, 578 and 713 of useful work).
+inline int pick_g16_tile_16(int64_t ncp);
+
+// Default: the 416-column g1_w tile when it pads the orbital columns by at
+// most 10% more than the best of the other tiles (at nao=2048, naux=8192,
+// nocc=400 on MI355X it took 35.7-36.2 ms against 37.0-37.3 for the
+// 208-column direct tile); else that other tile.
 inline int pick_g16_tile(int64_t ncp) {
+    const int other = pick_g16_tile_16(ncp);
+    const int64_t wo = kG16Tiles[other].cols;
+    const double pad_other = (double)(cdiv(ncp, wo) * wo), pad_w = (double)(cdiv(ncp, 416) * 416);
+    return pad_w <= 1.1 * pad_other ? 7 : other;
+}
+
+// The choice among the 16 x 16 x 32 tiles 0..6.
+inline int pick_g16_tile_16(int64_t ncp) {
     static const int cand[3] = {0, 1, 4};
     static const double rate[3] = {468.0, 740.0, 741.0};
     int best = 1;
@@ -623,33 +957,42 @@ inline int pick_g16_tile(int64_t ncp) {
 }
 
 template <typename H>
-void launch_g16(int t, hipStream_t st, const H* Bd, int64_t ldd, int64_t nao, const H* Ct, int64_t ncol,
+void launch_g16(int t, hipStream_t st, const H* Bd, int64_t ldd, int64_t rs, int64_t nao, const H* Ct, int64_t ncol,
                 int64_t ncp, H* X, int64_t naux) {
     switch (t) {
-        case 0: launch_g1<H, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
-        case 1: launch_g1<H, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
-        case 2: launch_g1<H, 13>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
-        case 3: launch_g1d<H, 2, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
-        case 4: launch_g1d<H, 2, 13>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
-        case 5: launch_g1d<H, 4, 8>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
-        default: launch_g1d<H, 4, 4>(st, Bd, ldd, nao, Ct, ncol, ncp, X, naux); break;
+        case 0: launch_g1<H, 4>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        case 1: launch_g1<H, 8>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        case 2: launch_g1<H, 13>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        case 3: launch_g1d<H, 2, 8>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        case 4: launch_g1d<H, 2, 13>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        case 5: launch_g1d<H, 4, 8>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        case 6: launch_g1d<H, 4, 4>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
+        default: launch_gw<H, 13, true, true>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
     }
 }
 
 // 16-bit GEMM2 output tiles (edge).  At nao=2048, naux=8192, nocc=400 the
 // 256 tile ran 687-695 TFLOP/s against 523-531 for the 128 tile; below
 // nao=1024 it would leave few tiles to split over, so the 128 tile stays.
-constexpr int kSyrk16Tiles[] = {128, 256};
-constexpr int kNumSyrk16Tiles = 2;
+// Index 2: the 256 tile on 32 x 32 x 16 steps (syrk_32, 8 wavefronts); at
+// nao=2048, naux=8192, nocc=400 it took 19.3-19.4 ms against 18.7-18.9 for
+// the 16 x 16 x 32 256 tile, which stays the default.
+constexpr int kSyrk16Tiles[] = {128, 256, 256};
+constexpr int kNumSyrk16Tiles = 3;
 inline int pick_syrk16_tile(int64_t nao) { return nao >= 1024 ? 1 : 0; }
 
 // Dense row length of the 16-bit copy (64-deep chunks) and the GEMM2 split:
 // about 2048 workgroups, and no FP32 running sum longer than kMaxSum16 terms
 // (the split partials are added in FP64).
 inline int64_t k16_ldd(int64_t nao) { return cdiv(nao, KC16) * KC16; }
+// Row stride of the dense copy and of Ct: ldd plus 64 elements, so that rows
+// are not a power-of-two number of bytes apart (at nao = 2048 a 4096-byte
+// stride sends the same chunk of every row to the same memory channel).
+inline int64_t k16_rs(int64_t ldd) { return ldd + 64; }
 
 struct K16Plan {
     int64_t ncp, T, ntl, nsplit, pchunk;
+    int kind;  // GEMM2 tile index
     size_t Bdense, Cw, X, kpart;  // bytes
 };
 
@@ -660,6 +1003,7 @@ K16Plan k16_plan(const dfjk_ctx* h, int64_t ncol) {
     int ts = h->k16_syrk_tile;
     if (ts < 0 || ts >= kNumSyrk16Tiles) ts = pick_syrk16_tile(nao);
     p.T = kSyrk16Tiles[ts];
+    p.kind = ts;
     const int64_t nt = cdiv(nao, p.T);
     p.ntl = nt * (nt + 1) / 2;
     int64_t nsplit = cdiv(2048, p.ntl);
@@ -667,8 +1011,8 @@ K16Plan k16_plan(const dfjk_ctx* h, int64_t ncol) {
     if (nsplit > naux) nsplit = naux;
     p.pchunk = cdiv(naux, nsplit);
     p.nsplit = cdiv(naux, p.pchunk);
-    p.Bdense = 2 * (size_t)naux * (size_t)(ldd * ldd);
-    p.Cw = 2 * (size_t)(p.ncp * ldd);
+    p.Bdense = 2 * (size_t)naux * (size_t)(ldd * k16_rs(ldd));
+    p.Cw = 2 * (size_t)(p.ncp * k16_rs(ldd));
     p.X = 2 * (size_t)(naux * nao * p.ncp);
     p.kpart = sizeof(float) * (size_t)(p.nsplit * p.ntl) * p.T * p.T;
     return p;
@@ -681,7 +1025,7 @@ int make_dense_t(dfjk_ctx* h) {
     if ((rc = h->Bdense.ensure(k16_plan(h, 1).Bdense))) return rc;
     const int64_t nt = cdiv(ldd, 64), ntile = nt * (nt + 1) / 2;
     dense_copy<H><<<dim3((unsigned)ntile, (unsigned)h->naux), kT, 0, h->stream>>>(
-        static_cast<const H*>(h->B), h->ldB, h->nao, ldd, ntile, static_cast<H*>(h->Bdense.ptr));
+        static_cast<const H*>(h->B), h->ldB, h->nao, ldd, k16_rs(ldd), ntile, static_cast<H*>(h->Bdense.ptr));
     DFJK_LAUNCH_CHECK("dense_copy");
     h->dense_ready = true;
     return DFJK_OK;
@@ -702,19 +1046,21 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     H* X = static_cast<H*>(h->X.ptr);
     const H* Bd = static_cast<const H*>(h->Bdense.ptr);
     h->prof.begin(PH_K, st);
-    c_transpose<H><<<dim3((unsigned)cdiv(ncp * ldd, 256)), 256, 0, st>>>(C, nao, ncol, ncp, ldd, Ct);
+    c_transpose<H><<<dim3((unsigned)cdiv(ncp * ldd, 256)), 256, 0, st>>>(C, nao, ncol, ncp, ldd, k16_rs(ldd), Ct);
     DFJK_LAUNCH_CHECK("c_transpose");
     h->prof.begin(PH_K_GEMM1, st);
     int t = h->k16_tile;
     if (t < 0 || t >= kNumG16Tiles) t = pick_g16_tile(ncp);
-    launch_g16<H>(t, st, Bd, ldd, nao, Ct, ncol, ncp, X, naux);
+    launch_g16<H>(t, st, Bd, ldd, k16_rs(ldd), nao, Ct, ncol, ncp, X, naux);
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
     const int64_t T = plan.T, ntl = plan.ntl, nsplit = plan.nsplit, pchunk = plan.pchunk;
     float* part = static_cast<float*>(h->kpart.ptr);
     const dim3 grid((unsigned)(ntl * nsplit));
     h->prof.begin(PH_K_SYRK, st);
-    if (T == 256)
+    if (plan.kind == 2)
+        syrk_32<H><<<grid, kT8, 0, st>>>(X, nao, ncp, naux, pchunk, ntl, ntl * nsplit, part);
+    else if (T == 256)
         syrk_16w<H><<<grid, kT, 0, st>>>(X, nao, ncp, naux, pchunk, ntl, ntl * nsplit, part);
     else
         syrk_16<H><<<grid, kT, 0, st>>>(X, nao, ncp, naux, pchunk, ntl, ntl * nsplit, part);
