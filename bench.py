@@ -464,7 +464,7 @@ def bench_c5(args):
             nconv += 1
             _, Dc = guess.core_guess(h, H, cfg.nocc)
             Xs.append(guess.features(H, Dc, R))
-            ts.append(guess.packed(D - Dc).float())
+            ts.append(guess.target(D, Dc))
         h.close()
         if seed % 200 == 0:
             log(f"  training data {seed}/{args.n_train}, {time.time() - t0:.0f} s")
@@ -478,7 +478,7 @@ def bench_c5(args):
            order_uniform=synth.uniform(2, synth.STREAM_MLP, X.shape[0] * args.epochs), log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - tt
-    core, learned, proj, fb, fails = [], [], [], 0, 0
+    core, learned, proj, fb, fails, wrong, wrong_p = [], [], [], 0, 0, 0, 0
     for seed in range(2000, 2000 + args.n_test):
         h, H, R = system(seed)
         ref, _, _ = guess.run_scf(h, H, cfg.nocc)
@@ -488,10 +488,15 @@ def bench_c5(args):
             continue
         e_ref = ref[-1][0]
         core.append(guess.builds_to(ref, e_ref))
-        out = guess.solve(h, tr, H, R, cfg.nocc, e_ref=e_ref)
-        learned.append(out["builds"])
+        out = guess.solve(h, tr, H, R, cfg.nocc)
+        acc = guess.account(out, e_ref, ref)
+        learned.append(acc["builds"])
         fb += out["fallback"]
-        proj.append(guess.solve(h, tr, H, R, cfg.nocc, e_ref=e_ref, projected=True)["builds"])
+        wrong += acc["wrong_state"]
+        outp = guess.solve(h, tr, H, R, cfg.nocc, projected=True)
+        accp = guess.account(outp, e_ref, ref)
+        proj.append(accp["builds"])
+        wrong_p += accp["wrong_state"]
         h.close()
     core, learned, proj = np.array(core, float), np.array(learned, float), np.array(proj, float)
     res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
@@ -507,7 +512,9 @@ def bench_c5(args):
            "paired_mean_difference": float((learned - core).mean()),
            "projected_builds_mean": float(proj.mean()),
            "projected_paired_mean_difference": float((proj - core).mean()),
-           "fallbacks": int(fb), "test_systems_not_converged_plain": int(fails),
+           "fallbacks": int(fb), "converged_to_other_state": int(wrong),
+           "projected_converged_to_other_state": int(wrong_p),
+           "test_systems_not_converged_plain": int(fails),
            "train_systems_converged": int(nconv), "train_pairs": int(X.shape[0]),
            "train_seconds": train_s, "plain_scf_ms_mean": float(np.mean(scf_ms))}
     print(json.dumps(res), flush=True)

@@ -354,6 +354,35 @@ int dfjk_batch_workspace_bytes(dfjk_batch b, size_t* bytes);
 void dfjk_batch_destroy(dfjk_batch b);
 
 /*
+ * SCF over a batch: dfjk_scf_step for every molecule at once (Sec. IV.A and
+ * IV.B: each molecule's mean-field iteration, DIIS by default).
+ *   H_list  host array of nmol device pointers, molecule i's core
+ *           Hamiltonian (nao_i x nao_i FP64, symmetric), in dfjk_batch_init
+ *           order.
+ *   dfjk_batch_scf_guess  core guess for every molecule: Cocc <- the nocc
+ *           lowest eigenvectors of H, D <- 2 Cocc Cocc^T, written into the
+ *           molecules' Cocc and D buffers; forgets the SCF histories.
+ *   dfjk_batch_scf_step   one iteration for every molecule: J(D) and
+ *           K(Cocc) with the batch build (on entry D = 2 Cocc Cocc^T, as the
+ *           guess and every step leave it; the molecules' J and K buffers
+ *           receive them), then F = H + J - K/2, E, e = FD - DF, DIIS (with
+ *           dfjk_scf_step's rule for dropping old vectors), aufbau, and the
+ *           next D and Cocc written in place.  info: host array of nmol
+ *           records or NULL; when given, the call waits and returns
+ *           DFJK_W_NOT_CONVERGED until every molecule has converged
+ *           (dfjk_scf_step's criteria and defaults), DFJK_E_NONFINITE for a
+ *           non-finite energy.
+ *   dfjk_batch_scf_reset  forget the SCF histories.
+ * The molecules' dense steps run on up to 8 worker streams forked from and
+ * joined back to the batch stream (not graph-capturable); each molecule keeps
+ * its own DIIS history and eigensolver workspace (about (5 + 2 * 8) nao^2
+ * doubles), allocated on first use.  nao <= 4096 per molecule.
+ */
+int dfjk_batch_scf_guess(dfjk_batch b, const double* const* H_list);
+int dfjk_batch_scf_step(dfjk_batch b, const double* const* H_list, dfjk_scf_info* info);
+int dfjk_batch_scf_reset(dfjk_batch b);
+
+/*
  * Learned initial guess (a guess density need not be idempotent, paper
  * Sec. IV.A.1).  A perceptron d_in -> hidden -> hidden -> 1 with SiLU
  * activations, FP32, trained on the GPU:
@@ -372,6 +401,15 @@ void dfjk_batch_destroy(dfjk_batch b);
  *   dfjk_guess_features  X (npair x 8 FP32, packed pair order) from H, the
  *                        core-guess density Dcore and positions R (nao x 3).
  *   dfjk_guess_assemble  D = Dcore + y, symmetric, from y (npair FP32).
+ *   dfjk_guess_target    t (npair FP32, packed pair order) = D - Dcore on the
+ *                        pairs: the training target for a converged D.
+ *   dfjk_guess_check     out (2 FP64, device) = [tr D, number of non-finite
+ *                        entries of D]: the checks that decide whether a
+ *                        guess is used or the core guess takes its place.
+ *   dfjk_gather_rows     Y[r] = X[idx[r]] for n rows of d FP32 values (idx:
+ *                        n int64 row indices < rows of X, device), e.g. a
+ *                        shuffled training order.
+ * All asynchronous on `stream`.
  */
 typedef struct dfjk_mlp_ctx* dfjk_mlp;
 int dfjk_mlp_init(dfjk_mlp* m, int d_in, int hidden, int64_t max_batch, void* stream);
@@ -386,6 +424,9 @@ int dfjk_guess_features(const double* H_dev, const double* Dcore_dev, const doub
                         float* X_dev, void* stream);
 int dfjk_guess_assemble(const float* y_dev, const double* Dcore_dev, int64_t nao, double* D_dev,
                         void* stream);
+int dfjk_guess_target(const double* D_dev, const double* Dcore_dev, int64_t nao, float* t_dev, void* stream);
+int dfjk_guess_check(const double* D_dev, int64_t nao, double* out_dev, void* stream);
+int dfjk_gather_rows(const float* X_dev, const int64_t* idx_dev, int64_t n, int d, float* Y_dev, void* stream);
 
 /*
  * Sustained matrix-core rate (TFLOP/s) of v_mfma_f64_16x16x4f64 (DFJK_F64),

@@ -57,6 +57,13 @@ struct dfjk_batch_ctx {
     int tile[dfjk::kBuckets];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // SCF iterations over the batch: one handle per molecule without B (its
+    // DIIS history and eigensolver state), and worker streams for the
+    // molecules' dense steps
+    std::vector<dfjk_ctx*> scf;
+    std::vector<hipStream_t> workers;
+    std::vector<hipEvent_t> worker_done;
+    hipEvent_t built = nullptr;
 };
 
 namespace dfjk {
@@ -203,6 +210,54 @@ int time_tiles(dfjk_batch_ctx* b, int reps, double* best_ms) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return rc;
+}
+
+// Per-molecule SCF handles and worker streams, made on first use.
+int scf_setup(dfjk_batch b) {
+    if (!b->scf.empty()) return DFJK_OK;
+    const int nw = std::min(b->nmol, 8);
+    for (int w = 0; w < nw; ++w) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        DFJK_HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        b->workers.push_back(s);
+        DFJK_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        b->worker_done.push_back(e);
+    }
+    DFJK_HIP_TRY(hipEventCreateWithFlags(&b->built, hipEventDisableTiming));
+    for (int i = 0; i < b->nmol; ++i) {
+        dfjk_ctx* h = new (std::nothrow) dfjk_ctx();
+        if (!h) {
+            ::dfjk::set_error("dfjk_batch_scf: host allocation failed");
+            return DFJK_E_OOM;
+        }
+        const MolDesc& d = b->mols[i];
+        h->device = b->device;
+        h->nao = d.nao;
+        h->naux = d.naux;
+        h->npair = d.npair;
+        h->dtype = b->dtype;
+        dfjk_default_options(&h->opts);
+        b->scf.push_back(h);
+    }
+    // molecules longest first, dealt round-robin to the worker streams
+    for (int j = 0; j < b->nmol; ++j) b->scf[b->order[j]]->stream = b->workers[j % nw];
+    return DFJK_OK;
+}
+
+// Fork the worker streams off the batch stream, run fn(i) for every molecule
+// on its worker stream, and join them back.
+template <typename F>
+int on_workers(dfjk_batch b, F fn) {
+    DFJK_HIP_TRY(hipEventRecord(b->built, b->stream));
+    for (hipStream_t s : b->workers) DFJK_HIP_TRY(hipStreamWaitEvent(s, b->built, 0));
+    int rc = DFJK_OK;
+    for (int j = 0; j < b->nmol && !rc; ++j) rc = fn(b->order[j]);
+    for (size_t w = 0; w < b->workers.size(); ++w) {
+        DFJK_HIP_TRY(hipEventRecord(b->worker_done[w], b->workers[w]));
+        DFJK_HIP_TRY(hipStreamWaitEvent(b->stream, b->worker_done[w], 0));
+    }
     return rc;
 }
 
@@ -494,9 +549,81 @@ int dfjk_batch_workspace_bytes(dfjk_batch b, size_t* bytes) {
     return DFJK_OK;
 }
 
+int dfjk_batch_scf_guess(dfjk_batch b, const double* const* H_list) {
+    clear_error();
+    if (!b || !H_list) {
+        set_error("dfjk_batch_scf_guess: null batch or H list");
+        return DFJK_E_INVALID;
+    }
+    for (int i = 0; i < b->nmol; ++i)
+        if (!H_list[i] || b->mols[i].nao > 4096) {
+            set_error("dfjk_batch_scf_guess: molecule %d has a null H or nao above 4096", i);
+            return DFJK_E_INVALID;
+        }
+    int rc;
+    if ((rc = scf_setup(b))) return rc;
+    return on_workers(b, [&](int i) {
+        const MolDesc& d = b->mols[i];
+        scf_reset(b->scf[i]);
+        return aufbau(b->scf[i], H_list[i], d.nocc, const_cast<double*>(d.C), const_cast<double*>(d.D));
+    });
+}
+
+int dfjk_batch_scf_reset(dfjk_batch b) {
+    clear_error();
+    if (!b) {
+        set_error("null batch handle");
+        return DFJK_E_INVALID;
+    }
+    for (dfjk_ctx* h : b->scf) scf_reset(h);
+    return DFJK_OK;
+}
+
+int dfjk_batch_scf_step(dfjk_batch b, const double* const* H_list, dfjk_scf_info* info) {
+    static_assert(sizeof(dfjk_scf_info) == 6 * sizeof(double) + 2 * sizeof(int), "record layout");
+    clear_error();
+    if (!b || !H_list) {
+        set_error("dfjk_batch_scf_step: null batch or H list");
+        return DFJK_E_INVALID;
+    }
+    for (int i = 0; i < b->nmol; ++i)
+        if (!H_list[i] || b->mols[i].nao > 4096) {
+            set_error("dfjk_batch_scf_step: molecule %d has a null H or nao above 4096", i);
+            return DFJK_E_INVALID;
+        }
+    int rc;
+    if ((rc = scf_setup(b))) return rc;
+    // J(D) and K(Cocc) of every molecule, the batch's phases on its stream
+    if ((rc = run_all(b, b->stream))) return rc;
+    std::vector<const void*> rec((size_t)b->nmol, nullptr);
+    rc = on_workers(b, [&](int i) {
+        const MolDesc& d = b->mols[i];
+        return scf_tail(b->scf[i], H_list[i], const_cast<double*>(d.D), const_cast<double*>(d.C), d.nocc, d.J,
+                        d.K, &rec[i]);
+    });
+    if (rc || !info) return rc;
+    for (int i = 0; i < b->nmol; ++i)
+        DFJK_HIP_TRY(hipMemcpyAsync(&info[i], rec[i], sizeof(dfjk_scf_info), hipMemcpyDeviceToHost, b->stream));
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    bool all = true;
+    for (int i = 0; i < b->nmol; ++i) {
+        if (!(info[i].e_tot == info[i].e_tot)) {
+            set_error("dfjk_batch_scf_step: non-finite energy for molecule %d", i);
+            return DFJK_E_NONFINITE;
+        }
+        all = all && info[i].converged;
+    }
+    return all ? DFJK_OK : DFJK_W_NOT_CONVERGED;
+}
+
 void dfjk_batch_destroy(dfjk_batch b) {
     if (!b) return;
     (void)hipStreamSynchronize(b->stream);
+    for (hipStream_t s : b->workers) (void)hipStreamSynchronize(s);
+    for (dfjk_ctx* h : b->scf) dfjk_destroy(h);
+    for (hipEvent_t e : b->worker_done) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->workers) (void)hipStreamDestroy(s);
+    if (b->built) (void)hipEventDestroy(b->built);
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     b->work.release();

@@ -135,6 +135,9 @@ int k_build_16(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double*
 int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, int flags,
              dfjk_scf_info* info);
 int scf_reset(dfjk_ctx* h);
+int scf_tail(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, const double* J,
+             const double* K, const void** rec);
+int scf_read_info(dfjk_ctx* h, const void* rec, dfjk_scf_info* info);
 int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D);
 int k_tile_count();
 int k_tile_info(int t, int* ni, int* wm);

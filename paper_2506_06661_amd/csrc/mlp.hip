@@ -176,6 +176,51 @@ __global__ void assemble_guess(const float* __restrict__ y, const double* __rest
     }
 }
 
+// t[p(mu,nu)] = D[mu][nu] - Dcore[mu][nu] for mu <= nu (FP32 training target)
+__global__ void guess_target(const double* __restrict__ D, const double* __restrict__ Dc, int64_t nao,
+                             float* __restrict__ t) {
+    const int64_t nu = blockIdx.x;
+    for (int64_t mu = threadIdx.x; mu <= nu; mu += blockDim.x)
+        t[nu * (nu + 1) / 2 + mu] = (float)(D[mu * nao + nu] - Dc[mu * nao + nu]);
+}
+
+// One workgroup: out[0] = tr D (fixed-order sum), out[1] = number of
+// non-finite entries of D.
+__global__ __launch_bounds__(256) void guess_check(const double* __restrict__ D, int64_t nao,
+                                                   double* __restrict__ out) {
+    __shared__ double s_tr[256];
+    __shared__ double s_bad[256];
+    double tr = 0.0, bad = 0.0;
+    for (int64_t e = threadIdx.x; e < nao * nao; e += 256) {
+        const double v = D[e];
+        if (!isfinite(v)) bad += 1.0;
+        if (e / nao == e % nao) tr += v;
+    }
+    s_tr[threadIdx.x] = tr;
+    s_bad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_tr[threadIdx.x] += s_tr[threadIdx.x + w];
+            s_bad[threadIdx.x] += s_bad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s_tr[0];
+        out[1] = s_bad[0];
+    }
+}
+
+// Y[r][:] = X[idx[r]][:] (rows of d FP32 values)
+__global__ void gather_rows(const float* __restrict__ X, const int64_t* __restrict__ idx, int64_t n, int d,
+                            float* __restrict__ Y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * d) return;
+    const int64_t r = e / d;
+    Y[e] = X[idx[r] * d + (e - r * d)];
+}
+
 constexpr int64_t kSlab = 2048;
 
 }  // namespace
@@ -438,6 +483,40 @@ int dfjk_guess_assemble(const float* y, const double* Dcore, int64_t nao, double
     }
     assemble_guess<<<dim3((unsigned)nao), 128, 0, (hipStream_t)stream>>>(y, Dcore, nao, D);
     DFJK_LAUNCH_CHECK("assemble_guess");
+    return DFJK_OK;
+}
+
+int dfjk_guess_target(const double* D, const double* Dcore, int64_t nao, float* t, void* stream) {
+    clear_error();
+    if (!D || !Dcore || !t || nao < 1 || nao > 65535) {
+        set_error("dfjk_guess_target: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    guess_target<<<dim3((unsigned)nao), 128, 0, (hipStream_t)stream>>>(D, Dcore, nao, t);
+    DFJK_LAUNCH_CHECK("guess_target");
+    return DFJK_OK;
+}
+
+int dfjk_guess_check(const double* D, int64_t nao, double* out, void* stream) {
+    clear_error();
+    if (!D || !out || nao < 1 || nao > 65535) {
+        set_error("dfjk_guess_check: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    guess_check<<<1, 256, 0, (hipStream_t)stream>>>(D, nao, out);
+    DFJK_LAUNCH_CHECK("guess_check");
+    return DFJK_OK;
+}
+
+int dfjk_gather_rows(const float* X, const int64_t* idx, int64_t n, int d, float* Y, void* stream) {
+    clear_error();
+    if (!X || !idx || !Y || n < 0 || d < 1) {
+        set_error("dfjk_gather_rows: bad arguments");
+        return DFJK_E_INVALID;
+    }
+    if (n == 0) return DFJK_OK;
+    gather_rows<<<dim3((unsigned)cdiv(n * d, 256)), 256, 0, (hipStream_t)stream>>>(X, idx, n, d, Y);
+    DFJK_LAUNCH_CHECK("gather_rows");
     return DFJK_OK;
 }
 

@@ -327,8 +327,7 @@ int scf_reset(dfjk_ctx* h) {
 
 int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, int flags,
              dfjk_scf_info* info) {
-    const int64_t n = h->nao, n2 = n * n;
-    const int space = h->opts.diis_space;
+    const int64_t n = h->nao;
     if (n > kMaxEighN) {
         set_error("dfjk_scf_step: nao=%lld above %d", (long long)n, kMaxEighN);
         return DFJK_E_INVALID;
@@ -337,9 +336,6 @@ int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, i
     int rc = scf_ws(h, true, ws);
     if (rc) return rc;
     h->scf_ready = true;
-    const hipStream_t st = h->stream;
-    const unsigned g2 = (unsigned)cdiv(n2, 256);
-
     // J and K of the current density
     if ((rc = j_build(h, D, ws.J, nullptr, nullptr))) return rc;
     if (flags & DFJK_SCF_C_VALID)
@@ -347,13 +343,42 @@ int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, i
     else
         rc = k_build_from_D(h, D, ws.K);
     if (rc) return rc;
-    fock_kernel<<<g2, 256, 0, st>>>(H, ws.J, ws.K, n2, ws.F);
+    const void* rec = nullptr;
+    if ((rc = scf_tail(h, H, D, C, nocc, ws.J, ws.K, &rec))) return rc;
+    if (info) return scf_read_info(h, rec, info);
+    return DFJK_OK;
+}
+
+int scf_read_info(dfjk_ctx* h, const void* rec, dfjk_scf_info* info) {
+    DFJK_HIP_TRY(hipMemcpyAsync(info, rec, sizeof(ScfRecord), hipMemcpyDeviceToHost, h->stream));
+    DFJK_HIP_TRY(hipStreamSynchronize(h->stream));
+    if (!(info->e_tot == info->e_tot)) {
+        set_error("dfjk_scf_step: non-finite energy at iteration %d", info->iter);
+        return DFJK_E_NONFINITE;
+    }
+    return info->converged ? DFJK_OK : DFJK_W_NOT_CONVERGED;
+}
+
+// Everything of an SCF iteration after J and K: Fock matrix, energies,
+// commutator, DIIS, aufbau, next D and C, on the handle's stream.  *rec gets
+// the device address of the iteration record.
+int scf_tail(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, const double* J,
+             const double* K, const void** rec) {
+    const int64_t n = h->nao, n2 = n * n;
+    const int space = h->opts.diis_space;
+    ScfWs ws;
+    int rc = scf_ws(h, true, ws);
+    if (rc) return rc;
+    h->scf_ready = true;
+    const hipStream_t st = h->stream;
+    const unsigned g2 = (unsigned)cdiv(n2, 256);
+    fock_kernel<<<g2, 256, 0, st>>>(H, J, K, n2, ws.F);
     DFJK_LAUNCH_CHECK("fock_kernel");
     {
         DotList l{};
         l.a[0] = D, l.b[0] = H;
-        l.a[1] = D, l.b[1] = ws.J;
-        l.a[2] = D, l.b[2] = ws.K;
+        l.a[1] = D, l.b[1] = J;
+        l.a[2] = D, l.b[2] = K;
         if ((rc = dots(st, l, 3, n2, ws.part, ws.en))) return rc;
     }
 
@@ -405,15 +430,7 @@ int scf_step(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, i
 
     h->scf_iter = iter;
     h->scf_count = m;
-    if (info) {
-        DFJK_HIP_TRY(hipMemcpyAsync(info, ws.rec, sizeof(ScfRecord), hipMemcpyDeviceToHost, st));
-        DFJK_HIP_TRY(hipStreamSynchronize(st));
-        if (!(info->e_tot == info->e_tot)) {
-            set_error("dfjk_scf_step: non-finite energy at iteration %d", iter);
-            return DFJK_E_NONFINITE;
-        }
-        return info->converged ? DFJK_OK : DFJK_W_NOT_CONVERGED;
-    }
+    *rec = ws.rec;
     return DFJK_OK;
 }
 

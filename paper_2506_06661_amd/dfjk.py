@@ -92,6 +92,11 @@ def lib():
         L.dfjk_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.dfjk_batch_destroy.argtypes = [vp]
         L.dfjk_batch_destroy.restype = None
+        L.dfjk_batch_scf_guess.argtypes = [vp, ctypes.POINTER(vp)]
+        L.dfjk_batch_scf_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(ScfInfo)]
+        L.dfjk_batch_scf_reset.argtypes = [vp]
+        for name in ("dfjk_batch_scf_guess", "dfjk_batch_scf_step", "dfjk_batch_scf_reset"):
+            getattr(L, name).restype = i32
         for name in ("dfjk_batch_init", "dfjk_batch_build", "dfjk_batch_capture", "dfjk_batch_launch",
                      "dfjk_batch_autotune", "dfjk_batch_get_tile", "dfjk_batch_set_tile",
                      "dfjk_batch_workspace_bytes"):
@@ -109,6 +114,11 @@ def lib():
         L.dfjk_mlp_destroy.restype = None
         L.dfjk_guess_features.argtypes = [vp, vp, vp, i64, vp, vp]
         L.dfjk_guess_assemble.argtypes = [vp, vp, i64, vp, vp]
+        L.dfjk_guess_target.argtypes = [vp, vp, i64, vp, vp]
+        L.dfjk_guess_check.argtypes = [vp, i64, vp, vp]
+        L.dfjk_gather_rows.argtypes = [vp, vp, i64, i32, vp, vp]
+        for name in ("dfjk_guess_target", "dfjk_guess_check", "dfjk_gather_rows"):
+            getattr(L, name).restype = i32
         for name in ("dfjk_mlp_init", "dfjk_mlp_set_params", "dfjk_mlp_get", "dfjk_mlp_forward",
                      "dfjk_mlp_loss_grad", "dfjk_mlp_adam", "dfjk_guess_features", "dfjk_guess_assemble"):
             getattr(L, name).restype = i32
@@ -315,6 +325,25 @@ class Batch:
     def set_tile(self, bucket: int, tile: int):
         return _check("dfjk_batch_set_tile", lib().dfjk_batch_set_tile(self.h, bucket, tile))
 
+    def _hlist(self, H_list):
+        if len(H_list) != len(self.mols):
+            raise ValueError("one H per molecule")
+        return (ctypes.c_void_p * len(H_list))(*[_ptr(H) for H in H_list])
+
+    def scf_guess(self, H_list):
+        self._H = self._hlist(H_list)
+        return _check("dfjk_batch_scf_guess", lib().dfjk_batch_scf_guess(self.h, self._H))
+
+    def scf_step(self, H_list, want_info: bool = True):
+        """One SCF iteration for every molecule; returns (rc, [ScfInfo] or None)."""
+        self._H = self._hlist(H_list)
+        info = (ScfInfo * len(self.mols))() if want_info else None
+        rc = lib().dfjk_batch_scf_step(self.h, self._H, info)
+        return _check("dfjk_batch_scf_step", rc), (list(info) if want_info else None)
+
+    def scf_reset(self):
+        return _check("dfjk_batch_scf_reset", lib().dfjk_batch_scf_reset(self.h))
+
     def workspace_bytes(self) -> int:
         n = ctypes.c_size_t()
         _check("dfjk_batch_workspace_bytes", lib().dfjk_batch_workspace_bytes(self.h, ctypes.byref(n)))
@@ -403,6 +432,20 @@ def dfjk_guess_features(H, Dcore, R, nao, X, stream=None):
 def dfjk_guess_assemble(y, Dcore, nao, D, stream=None):
     return _check("dfjk_guess_assemble", lib().dfjk_guess_assemble(_ptr(y), _ptr(Dcore), nao, _ptr(D),
                                                                     _stream(stream)))
+
+
+def dfjk_guess_target(D, Dcore, nao, t, stream=None):
+    return _check("dfjk_guess_target", lib().dfjk_guess_target(_ptr(D), _ptr(Dcore), nao, _ptr(t),
+                                                                _stream(stream)))
+
+
+def dfjk_guess_check(D, nao, out, stream=None):
+    return _check("dfjk_guess_check", lib().dfjk_guess_check(_ptr(D), nao, _ptr(out), _stream(stream)))
+
+
+def dfjk_gather_rows(X, idx, n, d, Y, stream=None):
+    return _check("dfjk_gather_rows", lib().dfjk_gather_rows(_ptr(X), _ptr(idx), n, d, _ptr(Y),
+                                                              _stream(stream)))
 
 
 PHASES = ("J", "J_rho", "J_out", "K", "K_gemm1", "K_syrk", "K_finish")

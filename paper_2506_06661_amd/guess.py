@@ -13,9 +13,12 @@ default accelerator is DIIS (Sec. IV.B).  This module drives the library:
                       core guess on the packed pairs.
 * ``guess_density``-- features -> network -> D0 = Dcore + correction.
 * ``solve``        -- SCF from the learned guess with the core guess as the
-                      fallback (non-finite D0, electron count off by more than
-                      25%, no convergence, or a converged energy different from
-                      a reference).
+                      fallback, decided from the run's own signals only
+                      (non-finite D0, electron count off by more than 25%, no
+                      convergence within max_iter).
+* ``account``      -- J/K builds to a reference energy for a ``solve`` result,
+                      computed after the run: a run that converged to another
+                      state counts as a failure with a core-guess run on top.
 
 Systems are passed in as arrays (H, packed B, positions R); nothing here
 draws random inputs except the seeded parameter initialisation, whose
@@ -108,11 +111,12 @@ def features(H: torch.Tensor, Dcore: torch.Tensor, R: torch.Tensor) -> torch.Ten
     return X
 
 
-def packed(M: torch.Tensor) -> torch.Tensor:
-    """Lower-triangle entries of a symmetric matrix in packed pair order."""
-    nao = M.shape[0]
-    r, c = torch.tril_indices(nao, nao, device=M.device)
-    return M[r, c]
+def target(D: torch.Tensor, Dcore: torch.Tensor) -> torch.Tensor:
+    """Training target D - Dcore on the packed pairs (FP32, library kernel)."""
+    nao = D.shape[0]
+    t = torch.empty(nao * (nao + 1) // 2, dtype=torch.float32, device=D.device)
+    _d.dfjk_guess_target(D, Dcore, nao, t)
+    return t
 
 
 class Trainer:
@@ -142,8 +146,12 @@ class Trainer:
         hist = []
         for ep in range(epochs):
             if order_uniform is not None:
+                # the shuffle order is data preparation (a sort of the supplied
+                # uniforms); the rows are gathered by the library
                 perm = torch.from_numpy(np.argsort(order_uniform[ep * n:(ep + 1) * n], kind="stable")).to(X.device)
-                Xe, te = X[perm].contiguous(), t[perm].contiguous()
+                Xe, te = torch.empty_like(X), torch.empty_like(t)
+                _d.dfjk_gather_rows(X, perm, n, X.shape[1], Xe)
+                _d.dfjk_gather_rows(t, perm, n, 1, te)
             else:
                 Xe, te = X, t
             tot = 0.0
@@ -186,28 +194,49 @@ def project(handle: _d.Handle, D0: torch.Tensor, nocc: int):
 
 
 def solve(handle: _d.Handle, trainer: Trainer, H: torch.Tensor, R: torch.Tensor, nocc: int,
-          e_ref: float | None = None, max_iter: int = 100, tol: float = 1e-6, projected: bool = False):
+          max_iter: int = 100, projected: bool = False):
     """SCF from the learned guess with the core guess as fallback.  With
     `projected`, the guess is first replaced by the closest idempotent density
-    of rank nocc (then the first exchange goes through C).  Returns a dict
-    with the build count to |E - e_ref| < tol (including a fallback run),
-    whether the fallback ran, and the records."""
+    of rank nocc (then the first exchange goes through C).  The fallback is
+    decided from this run's own signals: a guess with non-finite entries or an
+    electron count off by more than 25%, or an SCF that does not converge
+    within max_iter.  Returns a dict with the records of the learned run, the
+    records of the fallback run ([] if none), whether it ran and why."""
     D0 = guess_density(handle, trainer, H, R, nocc)
-    ok = bool(torch.isfinite(D0).all().item())
-    if ok:
-        ne = float(torch.trace(D0).item())
-        ok = abs(ne - 2 * nocc) <= 0.25 * 2 * nocc
-    C0 = None
-    if ok and projected:
-        C0, D0 = project(handle, D0, nocc)
-    recs = run_scf(handle, H, nocc, D0=D0, C0=C0, max_iter=max_iter)[0] if ok else []
-    conv = bool(recs) and recs[-1][2]
-    if conv and e_ref is not None and abs(recs[-1][0] - e_ref) > tol:
-        conv = False
-    builds = len(recs) if not conv else (builds_to(recs, e_ref, tol) if e_ref is not None else len(recs))
-    if conv:
-        return {"builds": builds, "fallback": False, "records": recs}
+    chk = torch.empty(2, dtype=torch.float64, device=H.device)
+    _d.dfjk_guess_check(D0, H.shape[0], chk)
+    tr_d, bad = (float(v) for v in chk.cpu())
+    reason = None
+    if bad > 0:
+        reason = "non-finite guess"
+    elif abs(tr_d - 2 * nocc) > 0.25 * 2 * nocc:
+        reason = "electron count"
+    recs = []
+    if reason is None:
+        C0 = None
+        if projected:
+            C0, D0 = project(handle, D0, nocc)
+        recs = run_scf(handle, H, nocc, D0=D0, C0=C0, max_iter=max_iter)[0]
+        if not (recs and recs[-1][2]):
+            reason = "not converged"
+    if reason is None:
+        return {"records": recs, "fallback": False, "reason": None, "fallback_records": []}
     fb = run_scf(handle, H, nocc, max_iter=max_iter)[0]
-    nb = builds_to(fb, e_ref, tol) if e_ref is not None else len(fb)
-    return {"builds": len(recs) + (nb if nb is not None else len(fb)), "fallback": True,
-            "records": recs + fb}
+    return {"records": recs, "fallback": True, "reason": reason, "fallback_records": fb}
+
+
+def account(out: dict, e_ref: float, core_records, tol: float = 1e-6) -> dict:
+    """J/K builds to |E - e_ref| < tol for a ``solve`` result, counted after
+    the run (e_ref, the plain SCF's converged energy, is the judge and takes
+    no part in the run).  A run that converged to another state counts as a
+    failure, with the plain core-guess run's builds added on top."""
+    recs = out["records"]
+    if out["fallback"]:
+        nb = builds_to(out["fallback_records"], e_ref, tol)
+        fb_len = len(out["fallback_records"])
+        return {"builds": len(recs) + (nb if nb is not None else fb_len), "wrong_state": False}
+    nb = builds_to(recs, e_ref, tol)
+    if nb is not None and abs(recs[-1][0] - e_ref) < tol:
+        return {"builds": nb, "wrong_state": False}
+    nc = builds_to(core_records, e_ref, tol)
+    return {"builds": len(recs) + (nc if nc is not None else len(core_records)), "wrong_state": True}
