@@ -471,6 +471,8 @@ def bench_c5(args):
     X = torch.cat(Xs).contiguous()
     t = torch.cat(ts).contiguous()
     mlp = pkg.MLP(8, 256, 65536)
+    if args.mlp_bf16:
+        mlp.set_compute(pkg.DFJK_BF16)
     tr = guess.Trainer(mlp, synth.uniform(1, synth.STREAM_MLP, mlp.nparam))
     torch.cuda.synchronize()
     tt = time.perf_counter()
@@ -502,7 +504,7 @@ def bench_c5(args):
     res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
            "value": float(learned.mean()), "unit": "J/K builds to 1e-6 Eh (mean)", "n_gpus": 1,
            "steps": int(len(learned)), "warmup": 0, "ms_per_step": float(np.mean(scf_ms)),
-           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64 SCF, f32 MLP",
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64 SCF, " + ("bf16" if args.mlp_bf16 else "f32") + " MLP",
            "data": "synthetic",
            "config": {"workload": f"learned guess: nao={cfg.nao}, naux={cfg.naux}, nocc={cfg.nocc}, "
                                   f"{args.n_train} training systems, {args.n_test} held out, "
@@ -675,6 +677,8 @@ def main():
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--n-test", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--mlp-bf16", action="store_true",
+                    help="c5: hidden-layer products of the network on the 16-bit matrix cores")
     ap.add_argument("--b-scale", type=float, default=None,
                     help="c5: scale of B in the SCF family (default: the generator's)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -886,7 +890,7 @@ def main():
         del Ld, Rd, Kp
     res["measured_mfma_ceiling_tflops"] = {
         "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
-        "bf16_16x16x32": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}
+        "bf16_32x32x16": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}
     hbm_read = pkg.dfjk_probe_hbm_read(Bd)
     res["measured_hbm_read_gbs"] = hbm_read
     res["j_frac_of_measured_hbm_read"] = res["j_hbm_gbs"] / hbm_read

@@ -397,6 +397,12 @@ int dfjk_batch_scf_reset(dfjk_batch b);
  *   dfjk_mlp_loss_grad   L = mean((f(X) - t)^2) and its gradient (kept in
  *                        the handle); L to loss_dev (device, may be NULL).
  *   dfjk_mlp_adam        one Adam step (Kingma & Ba) with the kept gradient.
+ *   dfjk_mlp_set_compute DFJK_F32 (default) or DFJK_BF16: with BF16 the
+ *                        hidden x hidden products of the forward pass, of
+ *                        the input gradient and of the weight gradient round
+ *                        their FP32 operands once to bfloat16 and run on the
+ *                        16-bit matrix cores (FP32 sums); parameters, Adam
+ *                        state and every other step stay FP32.
  * Features and guess for one system (nao <= 65535, device pointers):
  *   dfjk_guess_features  X (npair x 8 FP32, packed pair order) from H, the
  *                        core-guess density Dcore and positions R (nao x 3).
@@ -419,6 +425,7 @@ int dfjk_mlp_get(dfjk_mlp m, int which, float* host_out);
 int dfjk_mlp_forward(dfjk_mlp m, const float* X_dev, int64_t n, float* y_dev);
 int dfjk_mlp_loss_grad(dfjk_mlp m, const float* X_dev, const float* t_dev, int64_t n, float* loss_dev);
 int dfjk_mlp_adam(dfjk_mlp m, float lr, float beta1, float beta2, float eps);
+int dfjk_mlp_set_compute(dfjk_mlp m, int dtype);
 void dfjk_mlp_destroy(dfjk_mlp m);
 int dfjk_guess_features(const double* H_dev, const double* Dcore_dev, const double* R_dev, int64_t nao,
                         float* X_dev, void* stream);
@@ -430,7 +437,7 @@ int dfjk_gather_rows(const float* X_dev, const int64_t* idx_dev, int64_t n, int 
 
 /*
  * Sustained matrix-core rate (TFLOP/s) of v_mfma_f64_16x16x4f64 (DFJK_F64),
- * v_mfma_f32_16x16x4f32 (DFJK_F32) or v_mfma_f32_16x16x32_bf16 (DFJK_BF16),
+ * v_mfma_f32_16x16x4f32 (DFJK_F32) or v_mfma_f32_32x32x16_bf16 (DFJK_BF16),
  * measured with register-only kernels on the current device (waits).
  */
 int dfjk_probe_mfma(int dtype, double* tflops);

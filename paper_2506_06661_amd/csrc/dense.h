@@ -24,6 +24,11 @@ int sgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, flo
           const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
           int64_t ldc);
 
+// C = op(A) op(B) (no scaling, C overwritten) with the FP32 operands rounded
+// once to bfloat16 and products on the 16-bit matrix cores, FP32 sums.
+int bgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+          const float* B, int64_t ldb, float* C, int64_t ldc);
+
 // out[t] = a_t . b_t for t < nd, summed in a fixed order (bitwise reproducible).
 // part needs dots_part_elems(nd) doubles.
 int dots(hipStream_t st, const DotList& list, int nd, int64_t n, double* part, double* out);

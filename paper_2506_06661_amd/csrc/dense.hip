@@ -73,6 +73,71 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
             }
 }
 
+// C = op(A) op(B) with FP32 operands rounded once to bfloat16 (RNE) as they
+// are staged, products on v_mfma_f32_16x16x32_bf16, FP32 accumulation and
+// output.  64 x 64 tile per workgroup, 2 x 2 waves of 32 x 32 (2 x 2 steps of
+// 16 x 16); K in chunks of 32, both operands held k-contiguous in LDS (row =
+// m or n, 32 bfloat16 + 8 of padding: 16-byte pieces of 16 consecutive rows
+// fall on distinct banks).
+typedef __bf16 v8bf_d __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_d __attribute__((ext_vector_type(4)));
+constexpr int BK = 32, BROW = BK + 8;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void bgemm_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ A,
+                                                     int64_t lda, const float* __restrict__ B, int64_t ldb,
+                                                     float* __restrict__ C, int64_t ldc) {
+    __shared__ uint16_t sA[GT][BROW];  // sA[m][k] = bf16(op(A)[m][k])
+    __shared__ uint16_t sB[GT][BROW];  // sB[n][k] = bf16(op(B)[k][n])
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.y * GT, n0 = (int64_t)blockIdx.x * GT;
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    v4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < K; k0 += BK) {
+        for (int e = tid; e < BK * GT; e += 256) {
+            // element (m, k) of op(A) and (n, k) of op(B); the mapping reads
+            // memory contiguously
+            int k, m;
+            if (TA) { k = e / GT; m = e % GT; } else { m = e / BK; k = e % BK; }
+            const int64_t gm = m0 + m, gk = k0 + k;
+            float v = 0.f;
+            if (gm < M && gk < K) v = TA ? A[gk * lda + gm] : A[gm * lda + gk];
+            sA[m][k] = float_to_bf16_rne(v);
+            int kb, n;
+            if (TB) { n = e / BK; kb = e % BK; } else { kb = e / GT; n = e % GT; }
+            const int64_t gn = n0 + n, gkb = k0 + kb;
+            float w = 0.f;
+            if (gn < N && gkb < K) w = TB ? B[gn * ldb + gkb] : B[gkb * ldb + gn];
+            sB[n][kb] = float_to_bf16_rne(w);
+        }
+        __syncthreads();
+        u4_d a[2], b[2];
+        for (int q = 0; q < 2; ++q) {
+            a[q] = *reinterpret_cast<const u4_d*>(&sA[wm * 32 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+            b[q] = *reinterpret_cast<const u4_d*>(&sB[wn * 32 + q * 16 + (lane & 15)][8 * (lane >> 4)]);
+        }
+        for (int ti = 0; ti < 2; ++ti)
+            for (int tj = 0; tj < 2; ++tj) {
+                v8bf_d av, bv;
+                __builtin_memcpy(&av, &a[ti], 16);
+                __builtin_memcpy(&bv, &b[tj], 16);
+                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[ti][tj], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    // result row 4 (lane / 16) + r, column lane % 16 of each 16 x 16 block
+    for (int ti = 0; ti < 2; ++ti)
+        for (int tj = 0; tj < 2; ++tj)
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm * 32 + ti * 16 + 4 * (lane >> 4) + r;
+                const int64_t gn = n0 + wn * 32 + tj * 16 + (lane & 15);
+                if (gm < M && gn < N) C[gm * ldc + gn] = acc[ti][tj][r];
+            }
+}
+
 // ---------------------------------------------------------------- reductions
 // part[t * nblk + b] = sum over this block's slice of a_t . b_t
 constexpr int RT = 256, RBLK = 128;
@@ -320,6 +385,17 @@ int sgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, flo
           const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
           int64_t ldc) {
     return gemm_t<float>(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+int bgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+          const float* B, int64_t ldb, float* C, int64_t ldc) {
+    const dim3 grid((unsigned)cdiv(N, GT), (unsigned)cdiv(M, GT));
+    if (!ta && !tb) bgemm_kernel<false, false><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    else if (ta && !tb) bgemm_kernel<true, false><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    else if (!ta && tb) bgemm_kernel<false, true><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    else bgemm_kernel<true, true><<<grid, 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc);
+    DFJK_LAUNCH_CHECK("bgemm_kernel");
+    return DFJK_OK;
 }
 
 int dots(hipStream_t st, const DotList& list, int nd, int64_t n, double* part, double* out) {

@@ -4,7 +4,10 @@
 // guess density (Sec. IV.A.1), so the prediction is used as given.
 //
 // All arithmetic is FP32 on the matrix cores (products) and vector units
-// (activations, reductions, Adam).  Weight gradients contract over the batch
+// (activations, reductions, Adam); with the BF16 compute mode the three
+// hidden-layer products (forward, input gradient, weight gradient) round
+// their FP32 operands to bfloat16 and run on the 16-bit matrix cores with
+// FP32 sums.  Weight gradients contract over the batch
 // with the batch split into slabs whose partial products are added in a fixed
 // order, so a training step is bitwise reproducible.
 #include <new>
@@ -232,6 +235,7 @@ struct dfjk_mlp_ctx {
     int64_t max_batch = 0, nparam = 0;
     dfjk::DevBuf params, grads, m1, m2, act, part;
     int64_t step = 0;
+    int compute = DFJK_F32;  // DFJK_BF16: hidden-layer products on the 16-bit matrix cores
     // parameter blocks inside `params` / `grads`
     int64_t oW1, ob1, oW2, ob2, oW3, ob3;
 };
@@ -269,7 +273,11 @@ int forward(dfjk_mlp_ctx* m, const float* X, int64_t n, Act& a) {
         return rc;
     bias_silu<<<dim3((unsigned)cdiv(n * H, 256)), 256, 0, st>>>(a.Z1, P + m->ob1, n, H, a.A1);
     DFJK_LAUNCH_CHECK("bias_silu");
-    if ((rc = sgemm(st, false, true, n, H, H, 1.f, a.A1, H, P + m->oW2, H, 0.f, a.Z2, H))) return rc;
+    if (m->compute == DFJK_BF16)
+        rc = bgemm(st, false, true, n, H, H, a.A1, H, P + m->oW2, H, a.Z2, H);
+    else
+        rc = sgemm(st, false, true, n, H, H, 1.f, a.A1, H, P + m->oW2, H, 0.f, a.Z2, H);
+    if (rc) return rc;
     bias_silu<<<dim3((unsigned)cdiv(n * H, 256)), 256, 0, st>>>(a.Z2, P + m->ob2, n, H, a.A2);
     DFJK_LAUNCH_CHECK("bias_silu");
     rowdot<<<dim3((unsigned)cdiv(n, 4)), 256, 0, st>>>(a.A2, P + m->oW3, P + m->ob3, n, H, a.y);
@@ -277,15 +285,18 @@ int forward(dfjk_mlp_ctx* m, const float* X, int64_t n, Act& a) {
     return DFJK_OK;
 }
 
-// out (M x K) = sum over the batch of A[i][:]^T B[i][:] in slabs
-int batch_outer(dfjk_mlp_ctx* m, const float* A, int M, const float* B, int K, int64_t n, float* out) {
+// out (M x K) = sum over the batch of A[i][:]^T B[i][:] in slabs (with bf16
+// true, the slab products round A and B to bfloat16)
+int batch_outer(dfjk_mlp_ctx* m, const float* A, int M, const float* B, int K, int64_t n, float* out,
+                bool bf16 = false) {
     const hipStream_t st = m->stream;
     float* part = static_cast<float*>(m->part.ptr);
     const int64_t nslab = cdiv(n, kSlab);
     for (int64_t s = 0; s < nslab; ++s) {
         const int64_t i0 = s * kSlab, len = i0 + kSlab < n ? kSlab : n - i0;
-        int rc = sgemm(st, true, false, M, K, len, 1.f, A + i0 * M, M, B + i0 * K, K, 0.f,
-                       part + s * (int64_t)M * K, K);
+        float* ps = part + s * (int64_t)M * K;
+        int rc = bf16 ? bgemm(st, true, false, M, K, len, A + i0 * M, M, B + i0 * K, K, ps, K)
+                      : sgemm(st, true, false, M, K, len, 1.f, A + i0 * M, M, B + i0 * K, K, 0.f, ps, K);
         if (rc) return rc;
     }
     slab_finish<<<dim3((unsigned)cdiv((int64_t)M * K, 256)), 256, 0, st>>>(part, nslab, (int64_t)M * K, out);
@@ -433,16 +444,29 @@ int dfjk_mlp_loss_grad(dfjk_mlp m, const float* X, const float* t, int64_t n, fl
     // layer 2
     back_out<<<dim3((unsigned)cdiv(n * H, 256)), 256, 0, st>>>(a.gy, P + m->oW3, a.Z2, n, H, a.gZ2);
     DFJK_LAUNCH_CHECK("back_out");
-    if ((rc = batch_outer(m, a.gZ2, H, a.A1, H, n, G + m->oW2))) return rc;
+    const bool bf = m->compute == DFJK_BF16;
+    if ((rc = batch_outer(m, a.gZ2, H, a.A1, H, n, G + m->oW2, bf))) return rc;
     if ((rc = colsum(m, a.gZ2, nullptr, H, n, G + m->ob2))) return rc;
     // layer 1
-    if ((rc = sgemm(st, false, false, n, H, H, 1.f, a.gZ2, H, P + m->oW2, H, 0.f, a.gA1, H))) return rc;
+    rc = bf ? bgemm(st, false, false, n, H, H, a.gZ2, H, P + m->oW2, H, a.gA1, H)
+            : sgemm(st, false, false, n, H, H, 1.f, a.gZ2, H, P + m->oW2, H, 0.f, a.gA1, H);
+    if (rc) return rc;
     mul_dsilu<<<dim3((unsigned)cdiv(n * H, 256)), 256, 0, st>>>(a.gA1, a.Z1, n * H);
     DFJK_LAUNCH_CHECK("mul_dsilu");
     if ((rc = batch_outer(m, a.gA1, H, X, m->d_in, n, G + m->oW1))) return rc;
     if ((rc = colsum(m, a.gA1, nullptr, H, n, G + m->ob1))) return rc;
     if (loss_dev)
         DFJK_HIP_TRY(hipMemcpyAsync(loss_dev, a.loss, sizeof(float), hipMemcpyDeviceToDevice, st));
+    return DFJK_OK;
+}
+
+int dfjk_mlp_set_compute(dfjk_mlp m, int dtype) {
+    clear_error();
+    if (!m || (dtype != DFJK_F32 && dtype != DFJK_BF16)) {
+        set_error("dfjk_mlp_set_compute: null handle or dtype other than DFJK_F32 / DFJK_BF16");
+        return DFJK_E_INVALID;
+    }
+    m->compute = dtype;
     return DFJK_OK;
 }
 

@@ -1,6 +1,8 @@
 // Sustained matrix-core rate, measured with register-only kernels (no memory
-// traffic): every wavefront repeats independent 16x16 steps on eight
-// accumulators, eight wavefronts per SIMD.  Used to state how far the
+// traffic): every wavefront repeats independent steps on several
+// accumulators (8 for FP64 16x16x4, 16 for FP32 16x16x4, 4 for BF16
+// 32x32x16: enough independent chains for each shape to reach its measured
+// best on MI355X), eight wavefronts per SIMD.  Used to state how far the
 // exchange kernels sit from what the matrix cores sustain, beside the
 // published peaks.  Likewise the sustained HBM read rate of a plain
 // streaming kernel, the measured ceiling of the J passes.
@@ -12,8 +14,9 @@ namespace {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
-constexpr int kAcc = 8;
+constexpr int kAcc = 8, kAcc32 = 16, kAccBf = 4;
 
 __global__ __launch_bounds__(256) void probe_f64(double* out, int iters) {
     v4d acc[kAcc];
@@ -28,20 +31,21 @@ __global__ __launch_bounds__(256) void probe_f64(double* out, int iters) {
 }
 
 __global__ __launch_bounds__(256) void probe_f32(double* out, int iters) {
-    v4f acc[kAcc];
-    for (int t = 0; t < kAcc; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    v4f acc[kAcc32];
+    for (int t = 0; t < kAcc32; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
     const float a = threadIdx.x * 1e-3f, b = 1.0f;
     for (int it = 0; it < iters; ++it)
 #pragma unroll
-        for (int t = 0; t < kAcc; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        for (int t = 0; t < kAcc32; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
     float s = 0.f;
-    for (int t = 0; t < kAcc; ++t) s += acc[t][0];
+    for (int t = 0; t < kAcc32; ++t) s += acc[t][0];
     if (s == -1.f) out[0] = s;
 }
 
 __global__ __launch_bounds__(256) void probe_bf16(double* out, int iters) {
-    v4f acc[kAcc];
-    for (int t = 0; t < kAcc; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    v16f acc[kAccBf];
+    for (int t = 0; t < kAccBf; ++t)
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
     v8bf a, b;
     for (int j = 0; j < 8; ++j) {
         a[j] = (__bf16)(threadIdx.x * 1e-3f);
@@ -49,9 +53,9 @@ __global__ __launch_bounds__(256) void probe_bf16(double* out, int iters) {
     }
     for (int it = 0; it < iters; ++it)
 #pragma unroll
-        for (int t = 0; t < kAcc; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        for (int t = 0; t < kAccBf; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
     float s = 0.f;
-    for (int t = 0; t < kAcc; ++t) s += acc[t][0];
+    for (int t = 0; t < kAccBf; ++t) s += acc[t][0];
     if (s == -1.f) out[0] = s;
 }
 
@@ -152,7 +156,8 @@ extern "C" int dfjk_probe_mfma(int dtype, double* tflops) {
     DFJK_HIP_TRY(hipEventCreate(&e0));
     DFJK_HIP_TRY(hipEventCreate(&e1));
     const int blocks = cus * 8, iters = 2000;  // 8 workgroups of 4 waves per CU
-    const double per = dtype == DFJK_BF16 ? 16384.0 : 2048.0;
+    // flop per step times steps per iteration
+    const double per = dtype == DFJK_BF16 ? 32768.0 * kAccBf : 2048.0 * (dtype == DFJK_F32 ? kAcc32 : kAcc);
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {  // the first launch warms the clocks
         (void)hipEventRecord(e0, nullptr);
@@ -171,6 +176,6 @@ extern "C" int dfjk_probe_mfma(int dtype, double* tflops) {
         set_error("dfjk_probe_mfma: launch failed: %s", hipGetErrorString(le));
         return DFJK_E_HIP;
     }
-    *tflops = per * kAcc * iters * (double)blocks * 4.0 / (ms * 1e9);
+    *tflops = per * iters * (double)blocks * 4.0 / (ms * 1e9);
     return DFJK_OK;
 }

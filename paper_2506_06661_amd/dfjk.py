@@ -110,6 +110,8 @@ def lib():
         L.dfjk_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.dfjk_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp]
         L.dfjk_mlp_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        L.dfjk_mlp_set_compute.argtypes = [vp, i32]
+        L.dfjk_mlp_set_compute.restype = i32
         L.dfjk_mlp_destroy.argtypes = [vp]
         L.dfjk_mlp_destroy.restype = None
         L.dfjk_guess_features.argtypes = [vp, vp, vp, i64, vp, vp]
@@ -408,6 +410,10 @@ class MLP:
     def loss_grad(self, X, t, loss=None):
         return _check("dfjk_mlp_loss_grad", lib().dfjk_mlp_loss_grad(self.h, _ptr(X), _ptr(t), X.shape[0],
                                                                       _ptr(loss)))
+
+    def set_compute(self, dtype: int):
+        """DFJK_F32 (default) or DFJK_BF16 for the hidden-layer products."""
+        return _check("dfjk_mlp_set_compute", lib().dfjk_mlp_set_compute(self.h, dtype))
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         return _check("dfjk_mlp_adam", lib().dfjk_mlp_adam(self.h, lr, b1, b2, eps))

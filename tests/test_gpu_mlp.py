@@ -100,3 +100,83 @@ def test_guess_features_and_assembly(pkg):
     yh = host(y).astype(np.float64)
     assert np.array_equal(Dh, Dh.T)
     assert Dh[mu, nu] == Dc[mu, nu] + yh[p]
+
+
+def bf16_sigmas(params, X, t, u=2.0 ** -8):
+    """Standard deviations of the BF16 network's errors against the FP64 one
+    under the probabilistic model of rounding (independent relative errors,
+    uniform in [-u, u], variance u^2/3; Higham & Mary 2019).
+
+    Only the three hidden x hidden products round their operands (to
+    bfloat16, u = 2^-8): an entry a(1 + d_a) b(1 + d_b) errs by a b (d_a +
+    d_b), variance (a b)^2 2u^2/3, summed over the product's terms.  Those
+    errors are carried through the chain rule with the exact first and second
+    derivatives of SiLU at the oracle's pre-activations."""
+    W1, b1, W2, b2, W3, b3 = params
+    y, (X, z1, h1, z2, h2) = oracle.mlp_forward(params, X)
+    n = X.shape[0]
+    v = 2.0 * u * u / 3.0
+
+    def d2silu(x):
+        s = 1.0 / (1.0 + np.exp(-x))
+        return s * (1 - s) * (2 + x * (1 - 2 * s))
+
+    s_z2 = np.sqrt(v * (h1 ** 2) @ (W2 ** 2).T)                 # forward product
+    s_h2 = np.abs(oracle.dsilu(z2)) * s_z2
+    s_y = np.sqrt((s_h2 ** 2) @ (W3 ** 2).T)[:, 0]
+    gy = (2.0 / n) * (y - t)
+    s_gy = (2.0 / n) * s_y
+    gz2 = (gy[:, None] * W3) * oracle.dsilu(z2)
+    s_gz2 = np.sqrt((s_gy[:, None] * W3 * oracle.dsilu(z2)) ** 2 + (gy[:, None] * W3 * d2silu(z2) * s_z2) ** 2)
+    s_gW2 = np.sqrt(v * (gz2 ** 2).T @ (h1 ** 2) + (s_gz2 ** 2).T @ (h1 ** 2))   # weight-gradient product
+    s_gb2 = np.sqrt((s_gz2 ** 2).sum(0))
+    s_ga1 = np.sqrt(v * (gz2 ** 2) @ (W2 ** 2) + (s_gz2 ** 2) @ (W2 ** 2))      # input-gradient product
+    s_gz1 = np.abs(oracle.dsilu(z1)) * s_ga1
+    s_gW1 = np.sqrt((s_gz1 ** 2).T @ (X ** 2))
+    s_gb1 = np.sqrt((s_gz1 ** 2).sum(0))
+    s_gW3 = np.sqrt((s_gy[:, None] ** 2).T @ (h2 ** 2) + (gy[:, None] ** 2).T @ (s_h2 ** 2))
+    s_gb3 = np.array([np.sqrt((s_gy ** 2).sum())])
+    return s_y, [s_gW1, s_gb1, s_gW2, s_gb2, s_gW3, s_gb3]
+
+
+# The rounding of W2 is shared by every row of the batch, so batch sums of its
+# effects are partly correlated and the model's variances somewhat low: a
+# host emulation of the BF16 products (oracle arithmetic on rounded operands)
+# reaches up to 6 standard deviations; the assertion allows 16.
+LAMBDA = 16.0
+
+
+def test_mlp_bf16_gradients_within_bound(pkg):
+    """BF16 compute mode: forward values and every gradient entry within
+    LAMBDA standard deviations of bf16_sigmas plus the FP32 test's 1e-4 of the
+    largest entry (FP32 sums and the FP32 steps); the errors must also be
+    visibly larger than FP32's, showing the 16-bit products in use."""
+    from paper_2506_06661_amd import dfjk
+    m = pkg.MLP(d_in=8, hidden=256, max_batch=4096)
+    m.set_compute(dfjk.DFJK_BF16)
+    shapes = m.shapes()
+    params = [p.astype(np.float32).astype(np.float64) for p in glorot(shapes, 8)]
+    params[3] = (0.05 * synth.normal(8, 9, 256)).astype(np.float32).astype(np.float64)
+    m.set_params(np.concatenate([p.ravel() for p in params]))
+    rng = np.random.default_rng(6)
+    n = 3000
+    X = rng.standard_normal((n, 8)).astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    Xd, td = dev(X, torch.float32), dev(t, torch.float32)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    m.forward(Xd, y)
+    y_ref, _ = oracle.mlp_forward(params, X.astype(np.float64))
+    dy, dg = bf16_sigmas(params, X.astype(np.float64), t.astype(np.float64))
+    err_y = np.abs(host(y) - y_ref)
+    print(f"y: max err {err_y.max():.3e}, max sigma {dy.max():.3e}, max |y| {np.abs(y_ref).max():.3e}")
+    assert np.all(err_y <= LAMBDA * dy + 1e-4 * np.abs(y_ref).max())
+    assert err_y.max() > 5e-4 * np.abs(y_ref).max()  # far above FP32 rounding: the 16-bit products are in use
+    m.loss_grad(Xd, td)
+    _, g_ref = oracle.mlp_loss_grad(params, X.astype(np.float64), t.astype(np.float64))
+    g = m.unflatten(m.grads())
+    for k, (a, b, bd) in enumerate(zip(g, g_ref, dg)):
+        err = np.abs(a.reshape(b.shape) - b)
+        bd = bd.reshape(b.shape)
+        print(f"block {k}: max|g| {np.abs(b).max():.3e} err {err.max():.3e} max sigma {bd.max():.3e}")
+        assert np.all(err <= LAMBDA * bd + 1e-4 * np.abs(b).max() + 1e-12), k
+    m.close()
