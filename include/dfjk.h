@@ -297,7 +297,9 @@ int dfjk_profile_read(dfjk_handle h, double* total_ms, int* counts, int nphase);
 /*
  * Tile shapes (for autotuning).  DFJK_TILE_GEMM1 selects the X = B_P C
  * kernel's workgroup tile: dfjk_tile_info gives (p0, p1) = (row tiles of 16
- * occupied orbitals, column tiles of 16 basis functions per wavefront).
+ * occupied orbitals, column tiles of 16 basis functions per wavefront); the
+ * last three run on the FP32 32 x 32 x 2 matrix-core steps and have no FP64
+ * form (dfjk_set_tile returns DFJK_E_DTYPE for them on an FP64 handle).
  * DFJK_TILE_J_OUT selects the FP64 J pass-2 column width: (p0, p1) =
  * (packed columns per workgroup, 0).  DFJK_TILE_K16 selects the 16-bit
  * exchange's GEMM1 tile: (p0, p1) = (occupied orbitals, basis functions) per

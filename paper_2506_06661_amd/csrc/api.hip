@@ -383,6 +383,10 @@ int dfjk_set_tile(dfjk_handle h, int kernel, int index) {
         set_error("dfjk_set_tile: kernel %d / index %d invalid", kernel, index);
         return DFJK_E_INVALID;
     }
+    if (kernel == DFJK_TILE_GEMM1 && index >= 0 && !k_tile_has_dtype(index, h->dtype)) {
+        set_error("dfjk_set_tile: GEMM1 tile %d has no form for B dtype %d", index, h->dtype);
+        return DFJK_E_DTYPE;
+    }
     if (kernel == DFJK_TILE_GEMM1)
         h->g1_tile = index;
     else if (kernel == DFJK_TILE_J_OUT)

@@ -140,6 +140,7 @@ int scf_tail(dfjk_ctx* h, const double* H, double* D, double* C, int64_t nocc, c
 int scf_read_info(dfjk_ctx* h, const void* rec, dfjk_scf_info* info);
 int aufbau(dfjk_ctx* h, const double* F, int64_t nocc, double* C, double* D);
 int k_tile_count();
+bool k_tile_has_dtype(int t, int dtype);  // GEMM1 tile t has a form for B of this dtype
 int k_tile_info(int t, int* ni, int* wm);
 int k16_tile_count();
 int k16_tile_info(int t, int* cols, int* rows);

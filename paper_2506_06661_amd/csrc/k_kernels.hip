@@ -266,6 +266,93 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
             }
 }
 
+// FP32 form on v_mfma_f32_32x32x2f32 (4096 flop per step; lane l supplies
+// A[l%32][l/32] and B[l/32][l%32], result register r of lane l is row
+// 8(r/4) + 4(l/32) + r%4, column l%32): wavefront tile 32*NJ orbital columns
+// x 32*WJ basis functions, the four wavefronts stacked along mu.  Staging as
+// k_gemm1_body with (NI, WM) = (2 NJ, 2 WJ).  A wavefront holds NJ*WJ
+// independent 32 x 32 accumulators, whose longer steps keep the FP32 matrix
+// cores busy with far fewer chains than the 16 x 16 x 4 form needs (measured
+// register-only: 0.98 of the FP32 peak with 4 chains per wavefront).
+typedef float v16f_k __attribute__((ext_vector_type(16)));
+
+template <typename TS, int NJ, int WJ>
+__device__ inline void k_gemm1w_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
+                                     const float* __restrict__ C, int64_t ldc, int64_t ncol,
+                                     float* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb,
+                                     int64_t ioff = 0, int64_t iend = -1) {
+    constexpr int NI = 2 * NJ, WM = 2 * WJ;
+    constexpr int BI = 16 * NI, BM = 64 * WM;
+    if (iend < 0) iend = ncol;
+    __shared__ float sC[2][KC][g1_pitch_c<float, TS, NI, WM>()];
+    __shared__ float sB[2][KC][g1_pitch_b<float, TS, NI, WM>()];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
+    const int64_t i0 = ioff + ib * BI, mu0 = mb * BM;
+    const TS* Bp = B + P * ldB;
+
+    v16f_k acc[NJ][WJ];
+#pragma unroll
+    for (int a = 0; a < NJ; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+    const int64_t nchunks = cdiv(nao, KC);
+    G1Stage<float, NI, WM> st;
+    G1Addr<NI, WM> ad;
+    g1_addr_init<NI, WM>(ad, nao, ldc, iend, mu0, i0, tid);
+    g1_load<float, TS, NI, WM>(st, ad, Bp, nao, C, 0, mu0, tid);
+    g1_store<float, TS, NI, WM>(st, sC[0], sB[0], KC <= mu0, tid);
+    __syncthreads();
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        const int buf = ch & 1;
+        const int64_t nnext = (ch + 1) * KC;
+        const bool more = ch + 1 < nchunks;
+        if (more) {
+            g1_addr_next<NI, WM>(ad, ch * KC, ldc, tid);
+            g1_load<float, TS, NI, WM>(st, ad, Bp, nao, C, nnext, mu0, tid);
+        }
+#pragma unroll
+        for (int kp = 0; kp < KC / 2; ++kp) {
+            const int kr = kp * 2 + (lane >> 5);
+            float a[NJ], b[WJ];
+#pragma unroll
+            for (int t = 0; t < NJ; ++t) a[t] = sC[buf][kr][t * 32 + (lane & 31)];
+#pragma unroll
+            for (int t = 0; t < WJ; ++t)
+                b[t] = sB[buf][kr][(wave * 32 * WJ + t * 32 + (lane & 31)) ^ g1_swz<float, TS, NI, WM>(kr)];
+#pragma unroll
+            for (int ti = 0; ti < NJ; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < WJ; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+        }
+        if (more) g1_store<float, TS, NI, WM>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ti = 0; ti < NJ; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < WJ; ++tj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = i0 + ti * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t mu = mu0 + wave * 32 * WJ + tj * 32 + (lane & 31);
+                if (i < iend && mu < nao) X[(P * ncol + i) * ldx + mu] = acc[ti][tj][r];
+            }
+}
+
+template <typename TS, int NJ, int WJ>
+__global__ __launch_bounds__(kThreads) void k_gemm1w(const TS* __restrict__ B, int64_t ldB, int64_t nao,
+                                                      const float* __restrict__ C, int64_t ldc, int64_t ncol,
+                                                      float* __restrict__ X, int64_t ldx, int64_t nib,
+                                                      int64_t nmb, int64_t nblk, int64_t ioff, int64_t iend) {
+    k_gemm1w_body<TS, NJ, WJ>(xcd_logical(blockIdx.x, nblk), B, ldB, nao, C, ldc, ncol, X, ldx, nib, nmb,
+                              ioff, iend);
+}
+
 template <typename T, typename TS, int NI, int WM>
 __global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                                      const T* __restrict__ C, int64_t ldc, int64_t ncol,
@@ -483,6 +570,18 @@ int launch_gemm1(const dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_
     return DFJK_OK;
 }
 
+template <typename TS, int NJ, int WJ>
+int launch_gemm1w(const dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx, int64_t ioff,
+                  int64_t iend) {
+    const int64_t nib = cdiv(iend - ioff, 32 * NJ), nmb = cdiv(h->nao, 128 * WJ);
+    const int64_t nblk = nib * nmb * h->naux;
+    k_gemm1w<TS, NJ, WJ><<<dim3((unsigned)nblk), kThreads, 0, h->stream>>>(
+        static_cast<const TS*>(h->B), h->ldB, h->nao, static_cast<const float*>(C), ncol, ncol,
+        static_cast<float*>(X), ldx, nib, nmb, nblk, ioff, iend);
+    DFJK_LAUNCH_CHECK("k_gemm1w");
+    return DFJK_OK;
+}
+
 // Compiled GEMM1 tiles: (NI, WM) = (i tiles of 16, mu tiles of 16 per wave),
 // one launcher per B storage type (FP64 on the FP64 matrix cores; FP32, BF16
 // and FP16 dequantised exactly on load and run on the FP32 matrix cores).
@@ -498,11 +597,25 @@ struct G1Tile {
                 launch_gemm1<float, uint16_t, a, b>, launch_gemm1<float, _Float16, a, b>       \
         }                                                                                      \
     }
+// Tiles 14..16: the FP32 32 x 32 x 2 form, (NI, WM) = (2 NJ, 2 WJ); no FP64
+// launcher (FP64 has no 32 x 32 step).  Not defaults: at nao=1024,
+// naux=4096, nocc=200 (FP32 B) on MI355X they took 28.8 / 48.2 / 38.9 ms
+// against 24.9 ms for (5,1): the shared staging code needs 200-248 VGPRs for
+// their wider tiles, leaving 1-2 wavefronts per SIMD.
+#define G1W(a, b)                                                                              \
+    {                                                                                          \
+        2 * a, 2 * b, {                                                                        \
+            nullptr, launch_gemm1w<float, a, b>, launch_gemm1w<uint16_t, a, b>,                \
+                launch_gemm1w<_Float16, a, b>                                                  \
+        }                                                                                      \
+    }
 const G1Tile kG1Tiles[] = {
     G1T(1, 2), G1T(2, 2), G1T(3, 2), G1T(4, 2), G1T(5, 2), G1T(6, 2),
     G1T(7, 2), G1T(8, 2), G1T(13, 1), G1T(4, 4), G1T(7, 1), G1T(5, 1), G1T(6, 1), G1T(3, 1),
+    G1W(2, 1), G1W(1, 2), G1W(2, 2),
 };
 #undef G1T
+#undef G1W
 constexpr int kNumG1Tiles = sizeof(kG1Tiles) / sizeof(kG1Tiles[0]);
 constexpr int kFirstRestTile = 12;  // (6,1) and (3,1): defaults only for the rest of a split
 
@@ -564,8 +677,14 @@ G1Split pick_g1_split(int64_t ncol, bool f32) {
 // X = (B_P C)^T for every P, with the handle's forced tile or the default
 // split (profiled as the GEMM1 phase).
 int run_gemm1(dfjk_ctx* h, const void* C, int64_t ncol, void* X, int64_t ldx, bool f32) {
-    if (h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles)
-        return kG1Tiles[h->g1_tile].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, ncol);
+    if (h->g1_tile >= 0 && h->g1_tile < kNumG1Tiles) {
+        const G1Launch f = kG1Tiles[h->g1_tile].by_dtype[h->dtype];
+        if (!f) {
+            set_error("GEMM1 tile %d has no FP64 form", h->g1_tile);
+            return DFJK_E_INVALID;
+        }
+        return f(h, C, ncol, X, ldx, 0, ncol);
+    }
     G1Split sp = pick_g1_split(ncol, f32);
     int rc = kG1Tiles[sp.t0].by_dtype[h->dtype](h, C, ncol, X, ldx, 0, sp.n0);
     if (!rc && sp.n0 < ncol) rc = kG1Tiles[sp.t1].by_dtype[h->dtype](h, C, ncol, X, ldx, sp.n0, ncol);
@@ -743,11 +862,34 @@ int launch_kb_gemm1(hipStream_t st, int dtype, const MolDesc* mols, const PhaseL
     return DFJK_OK;
 }
 
+template <typename TS, int NJ, int WJ>
+__global__ __launch_bounds__(kThreads) void kb_gemm1w(const MolDesc* __restrict__ mols, PhaseList pl) {
+    const int64_t b = xcd_logical(blockIdx.x, pl.nblk);
+    const int j = find_mol_k(pl.prefix, pl.n, b);
+    const MolDesc& d = mols[pl.ids[j]];
+    k_gemm1w_body<TS, NJ, WJ>(b - pl.prefix[j], static_cast<const TS*>(d.B), d.ldB, d.nao, d.Cf, d.nocc,
+                              d.nocc, d.X, d.nao, d.g1_nib, d.g1_nmb);
+}
+
+template <int NJ, int WJ>
+int launch_kb_gemm1w(hipStream_t st, int dtype, const MolDesc* mols, const PhaseList& pl) {
+    const dim3 grid((unsigned)pl.nblk);
+    switch (dtype) {
+        case DFJK_F32: kb_gemm1w<float, NJ, WJ><<<grid, kThreads, 0, st>>>(mols, pl); break;
+        case DFJK_BF16: kb_gemm1w<uint16_t, NJ, WJ><<<grid, kThreads, 0, st>>>(mols, pl); break;
+        case DFJK_F16: kb_gemm1w<_Float16, NJ, WJ><<<grid, kThreads, 0, st>>>(mols, pl); break;
+        default: set_error("batched builds take FP32, BF16 or FP16 B"); return DFJK_E_DTYPE;
+    }
+    DFJK_LAUNCH_CHECK("kb_gemm1w");
+    return DFJK_OK;
+}
+
 typedef int (*KbLaunch)(hipStream_t, int, const MolDesc*, const PhaseList&);
 #define KBT(a, b) launch_kb_gemm1<a, b>
 const KbLaunch kKbTiles[] = {KBT(1, 2), KBT(2, 2), KBT(3, 2), KBT(4, 2), KBT(5, 2), KBT(6, 2),
                              KBT(7, 2), KBT(8, 2), KBT(13, 1), KBT(4, 4), KBT(7, 1), KBT(5, 1),
-                             KBT(6, 1), KBT(3, 1)};
+                             KBT(6, 1), KBT(3, 1), launch_kb_gemm1w<2, 1>, launch_kb_gemm1w<1, 2>,
+                             launch_kb_gemm1w<2, 2>};
 #undef KBT
 static_assert(sizeof(kKbTiles) / sizeof(kKbTiles[0]) == kNumG1Tiles, "tile tables differ");
 
@@ -830,6 +972,10 @@ int k_reserve(dfjk_ctx* h, int64_t max_ncol) {
 }
 
 int k_tile_count() { return kNumG1Tiles; }
+
+bool k_tile_has_dtype(int t, int dtype) {
+    return t >= 0 && t < kNumG1Tiles && dtype >= 0 && dtype < 4 && kG1Tiles[t].by_dtype[dtype] != nullptr;
+}
 
 int k_tile_info(int t, int* ni, int* wm) {
     if (t < 0 || t >= kNumG1Tiles) return DFJK_E_INVALID;

@@ -102,10 +102,41 @@ def test_every_gemm1_tile(pkg):
     K_ref = oracle.K_C(B, nao, C)
     h = pkg.Handle(dev(B), nao)
     Cd = dev(C)
+    nf64 = 0
+    for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_GEMM1)):
+        try:
+            pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_GEMM1, t)
+        except pkg.DFJKError as e:  # the FP32-only 32 x 32 x 2 tiles
+            assert e.code == -5
+            continue
+        nf64 += 1
+        K = host(h.K(C=Cd))
+        assert max_rel(K, K_ref) < TOL, (t, pkg.dfjk_tile_info(pkg.DFJK_TILE_GEMM1, t))
+    assert nf64 >= 14
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+def test_every_gemm1_tile_reduced(pkg, dtype):
+    """Each GEMM1 tile on B stored in FP32 / BF16 (FP32 matrix cores, the
+    32 x 32 x 2 tiles included) gives the oracle's K on the rounded B within
+    the FP32 sums' error (1e-5 of the largest entry; the sums run over nao
+    and naux * nocc terms)."""
+    nao, naux, nocc = 300, 21, 101
+    R, B, C = system(nao, naux, nocc, 27)
+    quant = {1: oracle.quantize_f32, 2: oracle.quantize_bf16}[dtype]
+    Bq = quant(B)
+    K_ref = oracle.K_C(Bq, nao, C)
+    Bd = torch.empty(B.shape, dtype={1: torch.float32, 2: torch.bfloat16}[dtype], device="cuda")
+    pkg.dfjk_quantize(dev(B), Bd, dtype, B.size)
+    h = pkg.Handle(Bd, nao, dtype=dtype)
+    Cd = dev(C)
+    K0 = host(h.K(C=Cd))  # default tiles
+    assert max_rel(K0, K_ref) < 1e-5
     for t in range(pkg.dfjk_tile_count(pkg.DFJK_TILE_GEMM1)):
         pkg.dfjk_set_tile(h.h, pkg.DFJK_TILE_GEMM1, t)
         K = host(h.K(C=Cd))
-        assert max_rel(K, K_ref) < TOL, (t, pkg.dfjk_tile_info(pkg.DFJK_TILE_GEMM1, t))
+        assert max_rel(K, K_ref) < 1e-5, (t, pkg.dfjk_tile_info(pkg.DFJK_TILE_GEMM1, t))
+        assert np.array_equal(K, K.T)
 
 
 @pytest.mark.parametrize("naux", [33, 1000])
