@@ -405,6 +405,16 @@ def bench_c4(args):
         eager = timed(bt.build, args.steps)
         bt.capture()
         graph = timed(bt.launch, args.steps)
+        k16 = None
+        if code != pkg.DFJK_F32:
+            # the exchange on the 16-bit matrix cores (GEMM1 on the packed triangle)
+            bt.set_k16(True)
+            e16 = timed(bt.build, args.steps)
+            bt.capture()
+            g16 = timed(bt.launch, args.steps)
+            k16 = {"graph_ms": g16, "eager_ms": e16, "molecules_per_s": len(sizes) / g16 * 1e3,
+                   "k_tflops_aggregate": kfl / g16 / 1e9, "speedup_vs_fp32_exchange": graph / g16,
+                   "workspace_gb": bt.workspace_bytes() / 1e9}
         singles = [pkg.Handle(m["B"], m["nao"], dtype=code) for m in mols[name]]
 
         def loop():
@@ -421,6 +431,8 @@ def bench_c4(args):
                        "k_tflops_aggregate": kfl / graph / 1e9, "j_bytes_gb": jbytes[name] / 1e9,
                        "tiles_by_bucket": tiles, "speedup_vs_loop": single / graph,
                        "speedup_vs_untuned": untuned / graph}
+        if k16 is not None:
+            res_d[name]["k16"] = k16
         log(name, res_d[name])
     res = {"metric": "DF-K TFLOP/s + J HBM GB/s vs FP64 plain; J/K builds to 1e-6 Eh",
            "value": res_d["f32"]["molecules_per_s"], "unit": "molecules/s", "n_gpus": 1,

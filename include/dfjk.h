@@ -352,6 +352,20 @@ int dfjk_batch_launch(dfjk_batch b);
 int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* best_ms);
 int dfjk_batch_get_tile(dfjk_batch b, int bucket, int* tile);
 int dfjk_batch_set_tile(dfjk_batch b, int bucket, int tile);
+/*
+ * dfjk_batch_set_k16(b, 1): K of every molecule on the 16-bit matrix cores
+ * (BF16 / FP16 B only; DFJK_E_DTYPE otherwise), Eq. eq:df:eri contracted
+ * with the occupied orbitals as in the single-molecule 16-bit exchange:
+ * C^T rounded once to the storage format, X_P = B_P C accumulated in FP32
+ * from the packed triangle and rounded to 16 bits, K = 2 sum X X^T in FP32
+ * with the split partials added in FP64.  Error against the FP64 oracle on
+ * the stored B with C rounded the same way: below 2u max|K| plus the FP32
+ * sums (u = 2^-8 BF16, 2^-11 FP16).  J is unchanged.  Allocates the 16-bit
+ * workspace (C^T, X, split partials: about naux nao ceil32(nocc) 2 bytes per
+ * molecule) on the first call; drops a recorded graph.  0 returns to the
+ * FP32 exchange.
+ */
+int dfjk_batch_set_k16(dfjk_batch b, int on);
 int dfjk_batch_workspace_bytes(dfjk_batch b, size_t* bytes);
 void dfjk_batch_destroy(dfjk_batch b);
 

@@ -64,6 +64,9 @@ struct dfjk_batch_ctx {
     std::vector<hipStream_t> workers;
     std::vector<hipEvent_t> worker_done;
     hipEvent_t built = nullptr;
+    // exchange on the 16-bit matrix cores (BF16 / FP16 B), off by default
+    bool k16 = false;
+    dfjk::DevBuf work16;
 };
 
 namespace dfjk {
@@ -80,6 +83,9 @@ int64_t phase_blocks(int kind, const MolDesc& d, int dtype) {
         case BP_CF32: return cdiv(d.nao * d.nocc, kT);
         case BP_SYRK: return d.ntl * d.nsplit;
         case BP_KFIN: return d.ntl;
+        case BP_CT16:
+        case BP_SYRK16:
+        case BP_KFIN16: return k16_batch_blocks(kind, 0, d);
         default: return 0;
     }
 }
@@ -102,6 +108,9 @@ int build_phases(dfjk_batch_ctx* b) {
             if (kind < 0) {
                 if (bucket_of(d.nocc) != bucket) continue;
                 nb = d.g1_nib * d.g1_nmb * d.naux;
+            } else if (kind == BP_G16) {
+                if (k16_batch_bucket(d) != bucket) continue;
+                nb = k16_batch_blocks(BP_G16, bucket, d);
             } else {
                 nb = phase_blocks(kind, d, b->dtype);
             }
@@ -112,9 +121,16 @@ int build_phases(dfjk_batch_ctx* b) {
         ph.prefix.push_back(acc);
         if (!ph.ids.empty()) b->phases.push_back(ph);
     };
-    for (int k : {BP_PACK, BP_RHO, BP_RHO_FIN, BP_OUT, BP_JFIN, BP_CF32}) add(k, 0);
-    for (int bk = 0; bk < kBuckets; ++bk) add(-1, bk);
-    for (int k : {BP_SYRK, BP_KFIN}) add(k, 0);
+    for (int k : {BP_PACK, BP_RHO, BP_RHO_FIN, BP_OUT, BP_JFIN}) add(k, 0);
+    if (b->k16) {
+        add(BP_CT16, 0);
+        for (int bk = 0; bk < 3; ++bk) add(BP_G16, bk);
+        for (int k : {BP_SYRK16, BP_KFIN16}) add(k, 0);
+    } else {
+        add(BP_CF32, 0);
+        for (int bk = 0; bk < kBuckets; ++bk) add(-1, bk);
+        for (int k : {BP_SYRK, BP_KFIN}) add(k, 0);
+    }
     size_t bytes = 0;
     for (auto& ph : b->phases) {
         ph.off_ids = (int64_t)bytes;
@@ -151,6 +167,7 @@ int run_phase(dfjk_batch_ctx* b, const Phase& ph, hipStream_t st) {
     const PhaseList pl = list_of(b, ph);
     if (ph.kind < 0) return k_batch_gemm1(st, b->dtype, b->tile[ph.bucket], mols, pl);
     if (ph.kind <= BP_JFIN) return j_batch_phase(st, ph.kind, b->dtype, mols, pl);
+    if (ph.kind >= BP_CT16) return k16_batch_phase(st, ph.kind, ph.bucket, b->dtype, mols, pl);
     return k_batch_phase(st, ph.kind, b->dtype, mols, pl);
 }
 
@@ -539,13 +556,54 @@ int dfjk_batch_autotune(dfjk_batch b, int reps, const char* cache_path, double* 
     return DFJK_OK;
 }
 
+int dfjk_batch_set_k16(dfjk_batch b, int on) {
+    clear_error();
+    if (!b || (on != 0 && on != 1)) {
+        set_error("dfjk_batch_set_k16: null batch or flag not 0/1");
+        return DFJK_E_INVALID;
+    }
+    if (on && b->dtype != DFJK_BF16 && b->dtype != DFJK_F16) {
+        set_error("dfjk_batch_set_k16: the 16-bit exchange needs BF16 or FP16 B");
+        return DFJK_E_DTYPE;
+    }
+    DFJK_HIP_TRY(hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    if (on && !b->work16.ptr) {
+        size_t total = 0;
+        auto take = [&](size_t bytes) {
+            const size_t off = total;
+            total += (bytes + 255) / 256 * 256;
+            return off;
+        };
+        std::vector<size_t> offs;
+        for (auto& d : b->mols) {
+            size_t ct, x, kp;
+            k16_batch_geometry(d, &ct, &x, &kp);
+            offs.push_back(take(ct));
+            offs.push_back(take(x));
+            offs.push_back(take(kp));
+        }
+        int rc;
+        if ((rc = b->work16.ensure(total))) return rc;
+        char* base = static_cast<char*>(b->work16.ptr);
+        for (size_t i = 0; i < b->mols.size(); ++i) {
+            MolDesc& d = b->mols[i];
+            d.Ct16 = base + offs[3 * i];
+            d.X16 = base + offs[3 * i + 1];
+            d.kpart16 = reinterpret_cast<float*>(base + offs[3 * i + 2]);
+        }
+    }
+    b->k16 = on != 0;
+    return build_phases(b);
+}
+
 int dfjk_batch_workspace_bytes(dfjk_batch b, size_t* bytes) {
     clear_error();
     if (!b || !bytes) {
         set_error("dfjk_batch_workspace_bytes: bad arguments");
         return DFJK_E_INVALID;
     }
-    *bytes = b->work.bytes + b->d_mols.bytes + b->lists.bytes;
+    *bytes = b->work.bytes + b->work16.bytes + b->d_mols.bytes + b->lists.bytes;
     return DFJK_OK;
 }
 
@@ -627,6 +685,7 @@ void dfjk_batch_destroy(dfjk_batch b) {
     drop_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     b->work.release();
+    b->work16.release();
     b->d_mols.release();
     b->lists.release();
     delete b;

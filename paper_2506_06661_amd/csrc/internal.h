@@ -167,6 +167,11 @@ struct MolDesc {
     int64_t nsplit, kchunk, ntl;
     int64_t g1_nib, g1_nmb;
     int vec;
+    // 16-bit exchange (BF16 / FP16 B on the 16-bit matrix cores)
+    void* Ct16;        // ncp16 x rs16, C^T rounded to the storage format
+    void* X16;         // naux x nao x ncp16
+    float* kpart16;    // nsplit16 x ntl x 128 x 128
+    int64_t ncp16, ldd16, rs16, pchunk16, nsplit16;
 };
 
 // A phase launch over a subset of molecules: ids (device, n entries, in
@@ -178,11 +183,22 @@ struct PhaseList {
     int64_t nblk;
 };
 
-enum BatchPhaseKind { BP_PACK = 0, BP_RHO, BP_RHO_FIN, BP_OUT, BP_JFIN, BP_CF32, BP_SYRK, BP_KFIN, BP_NKIND };
+enum BatchPhaseKind {
+    BP_PACK = 0, BP_RHO, BP_RHO_FIN, BP_OUT, BP_JFIN, BP_CF32, BP_SYRK, BP_KFIN,
+    BP_CT16, BP_G16, BP_SYRK16, BP_KFIN16, BP_NKIND
+};
 int j_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl);
 int k_batch_phase(hipStream_t st, int kind, int dtype, const MolDesc* mols, const PhaseList& pl);
 int k_batch_gemm1(hipStream_t st, int dtype, int tile, const MolDesc* mols, const PhaseList& pl);
 int pick_tile(int64_t ncol);
+// 16-bit exchange over a batch (k16.hip): per-molecule geometry (sets the
+// *16 fields except the pointers; bytes of Ct16, X16, kpart16), the GEMM1
+// bucket of a molecule, the blocks of a phase, and the launch of a phase
+// (BP_CT16, BP_G16 with its bucket, BP_SYRK16, BP_KFIN16).
+void k16_batch_geometry(MolDesc& d, size_t* ct_bytes, size_t* x_bytes, size_t* kpart_bytes);
+int k16_batch_bucket(const MolDesc& d);
+int64_t k16_batch_blocks(int kind, int bucket, const MolDesc& d);
+int k16_batch_phase(hipStream_t st, int kind, int bucket, int dtype, const MolDesc* mols, const PhaseList& pl);
 int tile_nb(int tile, int64_t nao, int64_t ncol, int64_t* nib, int64_t* nmb);
 
 // quantisation (quantize.hip)

@@ -26,7 +26,7 @@ constexpr int kThreads = 256;
 constexpr int kRhoRows = 4;     // rows of B per workgroup in pass 1
 
 // dt[p(mu,nu)] for all mu <= nu; one block per row nu of the packed triangle.
-__device__ inline void pack_density_body(int64_t nu, const double* __restrict__ D, int64_t nao,
+__device__ __attribute__((always_inline)) inline void pack_density_body(int64_t nu, const double* __restrict__ D, int64_t nao,
                                          double* __restrict__ dt) {
     const int64_t base = nu * (nu + 1) / 2;
     for (int64_t mu = threadIdx.x; mu <= nu; mu += kThreads) {
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void j_rho_f64(const double* __restrict__
     }
 }
 
-__device__ inline void rho_finish_body(int64_t P, const double* __restrict__ part, int64_t naux,
+__device__ __attribute__((always_inline)) inline void rho_finish_body(int64_t P, const double* __restrict__ part, int64_t naux,
                                        int nchunk, double* __restrict__ rho,
                                        double* __restrict__ rho_out) {
     if (P >= naux) return;
@@ -216,7 +216,7 @@ constexpr int kJOutU[] = {2, 4, 8, 16};
 constexpr int kNumJOut = 4;
 
 // J[nu,mu] = J[mu,nu] = sum_s jpart[s][p(mu,nu)]; one block per packed row nu.
-__device__ inline void j_finish_body(int64_t nu, const double* __restrict__ jpart, int64_t npair,
+__device__ __attribute__((always_inline)) inline void j_finish_body(int64_t nu, const double* __restrict__ jpart, int64_t npair,
                                      int nsplit, int64_t nao, double* __restrict__ J) {
     const int64_t base = nu * (nu + 1) / 2;
     for (int64_t mu = threadIdx.x; mu <= nu; mu += kThreads) {
@@ -304,7 +304,7 @@ __global__ void split_f64(const double* __restrict__ x, int64_t n, float* __rest
 }
 
 template <typename TB, int R, int ACC>
-__device__ inline void j_rho_red_body(int64_t bx, int c, const TB* __restrict__ B, int64_t ldB,
+__device__ __attribute__((always_inline)) inline void j_rho_red_body(int64_t bx, int c, const TB* __restrict__ B, int64_t ldB,
                                       int64_t naux, int64_t npair, const double* __restrict__ dt,
                                       const float* __restrict__ dhi, const float* __restrict__ dlo,
                                       int64_t chunk, int nchunk, bool vec, double* __restrict__ part) {
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void j_rho_red(const TB* __restrict__ B, 
 // With DG the stream also sums B[P,p]^2 in FP64 (exact products of the
 // stored values) into dpart: the DF diagonal.
 template <typename TB, int ACC, bool DG = false>
-__device__ inline void j_out_red_body(int64_t bx, int s, const TB* __restrict__ B, int64_t ldB,
+__device__ __attribute__((always_inline)) inline void j_out_red_body(int64_t bx, int s, const TB* __restrict__ B, int64_t ldB,
                                       int64_t naux, int64_t npair, const double* __restrict__ rho,
                                       const float* __restrict__ rhi, const float* __restrict__ rlo,
                                       int64_t prows, bool vec, double* __restrict__ jpart,

@@ -382,14 +382,12 @@ __device__ inline void s16_store(const S16Stage& st, H (*sA)[LROW], H (*sB)[LROW
 }
 
 template <typename H>
-__global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t nao, int64_t ncp,
-                                               int64_t naux, int64_t pchunk, int64_t ntl, int64_t nblk,
-                                               float* __restrict__ part) {
+__device__ __attribute__((always_inline)) inline void syrk16_body(int64_t lid, const H* __restrict__ X, int64_t nao, int64_t ncp, int64_t naux,
+                                   int64_t pchunk, int64_t ntl, float* __restrict__ part) {
     __shared__ H sA[2][128][LROW];
     __shared__ H sB[2][128][LROW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int64_t lid = xcd_lid(blockIdx.x, nblk);
     const int64_t t = lid % ntl, s = lid / ntl;
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
@@ -442,6 +440,13 @@ __global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t n
                 const int n = wn * 64 + tj * 16 + (lane & 15);
                 out[m * 128 + n] = acc[ti][tj][r];
             }
+}
+
+template <typename H>
+__global__ __launch_bounds__(kT) void syrk_16(const H* __restrict__ X, int64_t nao, int64_t ncp,
+                                               int64_t naux, int64_t pchunk, int64_t ntl, int64_t nblk,
+                                               float* __restrict__ part) {
+    syrk16_body<H>(xcd_lid(blockIdx.x, nblk), X, nao, ncp, naux, pchunk, ntl, part);
 }
 
 // Lower tile (I >= J) of 256 x 256 of K; 2 x 2 waves of 128 x 128 (64
@@ -733,6 +738,210 @@ __global__ __launch_bounds__(kT8, 1) void g1_w(const H* __restrict__ Bd, int64_t
             }
 }
 
+// ---------------------------------------------------------------- GEMM1 on the packed triangle
+// X[P][mu][i] = sum_nu B_P[mu][nu] Ct[i][nu] with B_P read straight from the
+// packed lower triangle (element (a, b), a >= b, at a(a+1)/2 + b): no dense
+// copy.  Workgroup: WM x WN wavefronts of FM x FN result blocks of 16 x 16,
+// i.e. a BM = 16 FM WM by BI = 16 FN WN output tile of one P.  Per 64-deep
+// chunk of nu the BM rows of B_P are staged in LDS as rows mu, nu contiguous:
+//   below the diagonal (every nu <= every mu) packed row mu holds the chunk
+//     contiguously: 16-byte loads at any 2-byte alignment, stored as loaded;
+//   above it (every nu >= every mu) packed row nu holds mu contiguously: rows
+//     nu and nu + 1 are loaded at 8 consecutive mu and interleaved into the
+//     8 words (B[mu][nu], B[mu][nu + 1]), one 4-byte LDS store each;
+//   the chunks crossing the diagonal element by element.
+// Piece p of LDS row r sits at p ^ (r & 7) ^ ((r >> 3) & 7): the operand
+// reads (16 consecutive rows, one piece) keep one row per piece within each
+// 8 rows, and the word stores of 8 row-octets at one column land in 8
+// different pieces.
+constexpr int KCP = 64;
+__device__ inline int swzp(int row, int piece) { return (piece ^ (row & 7) ^ ((row >> 3) & 7)) * 8; }
+
+template <int WM, int WN, int FM, int FN>
+struct G1P {
+    static constexpr int NT = 64 * WM * WN, BM = 16 * FM * WM, BI = 16 * FN * WN;
+    static constexpr int PB = 8 * BM / NT;             // B pieces per thread (two per above-diagonal unit)
+    static constexpr int PC = (8 * BI + NT - 1) / NT;  // Ct pieces per thread
+    static_assert((8 * BM) % NT == 0 && PB % 2 == 0, "tile shape");
+};
+
+template <typename H, int WM, int WN, int FM, int FN>
+__device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, const H* __restrict__ Bp, int64_t ldB, int64_t nao,
+                                const H* __restrict__ Ct, int64_t rs, int64_t ncol, int64_t ncp,
+                                H* __restrict__ X, int64_t nib, int64_t nmb) {
+    using G = G1P<WM, WN, FM, FN>;
+    constexpr int BM = G::BM, BI = G::BI, NT = G::NT, PB = G::PB, PC = G::PC, OCT = BM / 8;
+    __shared__ uint16_t sA[2][BM][KCP];
+    __shared__ uint16_t sC[2][BI][KCP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
+    const int64_t i0 = ib * BI, mu0 = mb * BM;
+    const uint16_t* Bw = reinterpret_cast<const uint16_t*>(Bp) + P * ldB;
+    const uint16_t* Cw = reinterpret_cast<const uint16_t*>(Ct);
+    // Ct pieces e = tid + j NT: row i0 + e/8, piece e%8 (rows past ncp read
+    // row 0 and are stored as zeros)
+    const uint16_t* csrc[PC];
+    bool cok[PC];
+#pragma unroll
+    for (int j = 0; j < PC; ++j) {
+        const int e = tid + j * NT;
+        cok[j] = e < 8 * BI && i0 + (e >> 3) < ncp;
+        csrc[j] = Cw + (cok[j] ? i0 + (e >> 3) : 0) * rs + 8 * (e & 7);
+    }
+    // below-diagonal pieces e = tid + j NT: packed row mu0 + e/8 (rows past
+    // nao read row 0, which holds the chunk too, and are stored as zeros)
+    int64_t trow[PB];
+    bool rok[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+        const int64_t mu = mu0 + ((tid + j * NT) >> 3);
+        rok[j] = mu < nao;
+        trow[j] = rok[j] ? mu * (mu + 1) / 2 : 0;
+    }
+    const u4 z4 = u4{0u, 0u, 0u, 0u};
+    u4 sb[PB], sc[PC];
+    auto below = [&](int64_t nu0) { return nu0 + KCP <= mu0 + 1; };
+    auto above = [&](int64_t nu0) { return nu0 >= mu0 + BM - 1; };
+    auto load = [&](int64_t nu0) {
+#pragma unroll
+        for (int j = 0; j < PC; ++j) sc[j] = *reinterpret_cast<const u4*>(csrc[j] + nu0);
+        if (below(nu0)) {
+#pragma unroll
+            for (int j = 0; j < PB; ++j) __builtin_memcpy(&sb[j], Bw + trow[j] + nu0 + 8 * ((tid + j * NT) & 7), 16);
+        } else if (above(nu0)) {
+            // unit u: rows nu0 + 2q, + 1 at mu0 + 8o .. + 7 (q < 32, o < BM/8);
+            // rows past nao read row 0 at the same columns, which lie below
+            // nu0 <= nao - 1, and are stored as zeros
+#pragma unroll
+            for (int u = 0; u < PB / 2; ++u) {
+                const int e = tid + u * NT, o = e % OCT, q = e / OCT;
+                const int64_t nu = nu0 + 2 * q;
+                const int64_t t0 = nu < nao ? nu * (nu + 1) / 2 : 0;
+                const int64_t t1 = nu + 1 < nao ? (nu + 1) * (nu + 2) / 2 : 0;
+                __builtin_memcpy(&sb[2 * u], Bw + t0 + mu0 + 8 * o, 16);
+                __builtin_memcpy(&sb[2 * u + 1], Bw + t1 + mu0 + 8 * o, 16);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const int e = tid + j * NT;
+                const int64_t mu = mu0 + (e >> 3);
+                uint32_t w[4];
+#pragma unroll
+                for (int t = 0; t < 8; t += 2) {
+                    uint32_t h2[2];
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        const int64_t nu = nu0 + 8 * (e & 7) + t + d;
+                        const int64_t a = mu > nu ? mu : nu, b = mu > nu ? nu : mu;
+                        h2[d] = (mu < nao && nu < nao) ? (uint32_t)Bw[a * (a + 1) / 2 + b] : 0u;
+                    }
+                    w[t >> 1] = h2[0] | (h2[1] << 16);
+                }
+                sb[j] = u4{w[0], w[1], w[2], w[3]};
+            }
+        }
+    };
+    auto store = [&](int buf, int64_t nu0) {
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+            const int e = tid + j * NT;
+            if (e < 8 * BI) *reinterpret_cast<u4*>(&sC[buf][e >> 3][swz(e >> 3, e & 7)]) = cok[j] ? sc[j] : z4;
+        }
+        if (above(nu0)) {
+#pragma unroll
+            for (int u = 0; u < PB / 2; ++u) {
+                const int e = tid + u * NT, o = e % OCT, q = e / OCT;
+                const int64_t nu = nu0 + 2 * q;
+                const u4 a = nu < nao ? sb[2 * u] : z4, b = nu + 1 < nao ? sb[2 * u + 1] : z4;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const uint32_t lo = (a[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+                    const uint32_t hi = (b[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+                    const int r = 8 * o + m;
+                    *reinterpret_cast<uint32_t*>(&sA[buf][r][swzp(r, q >> 2) + 2 * (q & 3)]) = lo | (hi << 16);
+                }
+            }
+        } else {
+            const bool bl = below(nu0);
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const int e = tid + j * NT, r = e >> 3;
+                *reinterpret_cast<u4*>(&sA[buf][r][swzp(r, e & 7)]) = (!bl || rok[j]) ? sb[j] : z4;
+            }
+        }
+    };
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int64_t nk = cdiv(nao, KCP);  // Ct holds zeros from nao to the next multiple of 64
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nk;
+        if (more) load((kc + 1) * KCP);
+#pragma unroll
+        for (int ks = 0; ks < KCP / KS; ++ks) {
+            const int pc = ks * (KS / 8) + (lane >> 4);
+            u4 a[FM], b[FN];
+#pragma unroll
+            for (int f = 0; f < FM; ++f) {
+                const int r = wm * 16 * FM + f * 16 + (lane & 15);
+                a[f] = *reinterpret_cast<const u4*>(&sA[buf][r][swzp(r, pc)]);
+            }
+#pragma unroll
+            for (int n = 0; n < FN; ++n) {
+                const int r = wn * 16 * FN + n * 16 + (lane & 15);
+                b[n] = *reinterpret_cast<const u4*>(&sC[buf][r][swz(r, pc)]);
+            }
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+#pragma unroll
+                for (int f = 0; f < FM; ++f) acc[f][n] = Mma16<H>::step(a[f], b[n], acc[f][n]);
+            if constexpr (FN >= 8) {
+                // wide tiles: several operand reads in flight ahead of the
+                // products: R0 reads, then (FM products, 1 read) until the
+                // reads run out (narrow tiles keep the compiler's order, which
+                // needs half the registers)
+                constexpr int NR = FM + FN, R0 = 6 < NR ? 6 : NR;
+                __builtin_amdgcn_sched_group_barrier(0x100, R0, 0);
+#pragma unroll
+                for (int g = 0; g < NR - R0; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - FM * (NR - R0), 0);
+            }
+        }
+        if (more) store(buf ^ 1, (kc + 1) * KCP);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < FM; ++f)
+#pragma unroll
+        for (int n = 0; n < FN; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t mu = mu0 + wm * 16 * FM + f * 16 + 4 * (lane >> 4) + r;
+                const int64_t i = i0 + wn * 16 * FN + n * 16 + (lane & 15);
+                if (mu < nao && i < ncp)
+                    X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[f][n][r] : 0.f);
+            }
+}
+
+template <typename H, int WM, int WN, int FM, int FN>
+__global__ __launch_bounds__(64 * WM * WN) void g1_p(const H* __restrict__ Bp, int64_t ldB, int64_t nao,
+                                                      const H* __restrict__ Ct, int64_t rs, int64_t ncol,
+                                                      int64_t ncp, H* __restrict__ X, int64_t nib, int64_t nmb,
+                                                      int64_t nblk) {
+    g1p_body<H, WM, WN, FM, FN>(xcd_lid(blockIdx.x, nblk), Bp, ldB, nao, Ct, rs, ncol, ncp, X, nib, nmb);
+}
+
 // GEMM2 on 256 x 256 lower tiles of K with 8 wavefronts (4 along mu x 2
 // along nu, 64 x 128 each = 2 x 4 result blocks of 32 x 32 on 32 x 32 x 16
 // steps).  The contraction over (P, i) runs in 32-wide steps inside each P;
@@ -858,13 +1067,12 @@ __global__ __launch_bounds__(kT8, 1) void syrk_32(const H* __restrict__ X, int64
 // grid: kFin16 blocks per lower tile, each adding up a contiguous slice of it
 // (kFin16 workgroups per 128 x 128 block of the tile)
 template <int TS>
-__global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ part, int64_t nsplit,
-                                                     int64_t ntl, int64_t nao, double scale,
-                                                     double* __restrict__ K) {
+__device__ __attribute__((always_inline)) inline void syrk16_finish_body(int64_t bid, const float* __restrict__ part, int64_t nsplit, int64_t ntl,
+                                          int64_t nao, double scale, double* __restrict__ K) {
     constexpr int nsub = kFin16 * (TS / 128) * (TS / 128);
     constexpr int per = TS * TS / nsub;
-    const int64_t t = blockIdx.x / nsub;
-    const int sub = (int)(blockIdx.x % nsub);
+    const int64_t t = bid / nsub;
+    const int sub = (int)(bid % nsub);
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while (I * (I + 1) / 2 > t) --I;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -882,6 +1090,13 @@ __global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ pa
         K[mu * nao + nu] = v;
         K[nu * nao + mu] = v;
     }
+}
+
+template <int TS>
+__global__ __launch_bounds__(kT) void syrk16_finish(const float* __restrict__ part, int64_t nsplit,
+                                                     int64_t ntl, int64_t nao, double scale,
+                                                     double* __restrict__ K) {
+    syrk16_finish_body<TS>(blockIdx.x, part, nsplit, ntl, nao, scale, K);
 }
 
 template <typename H, int NI>
@@ -908,6 +1123,16 @@ void launch_gw(hipStream_t st, const H* Bd, int64_t ldd, int64_t rs, int64_t nao
     g1_w<H, NI, PRE, SCHED><<<dim3((unsigned)nblk), kT8, 0, st>>>(Bd, ldd, rs, nao, Ct, ncol, ncp, X, nib, nmb, nblk);
 }
 
+template <typename H, int WM, int WN, int FM, int FN>
+void launch_gp(hipStream_t st, const H* Bp, int64_t ldB, int64_t nao, const H* Ct, int64_t rs, int64_t ncol,
+               int64_t ncp, H* X, int64_t naux) {
+    using G = G1P<WM, WN, FM, FN>;
+    const int64_t nib = cdiv(ncp, G::BI), nmb = cdiv(nao, G::BM);
+    const int64_t nblk = nib * nmb * naux;
+    g1_p<H, WM, WN, FM, FN><<<dim3((unsigned)nblk), G::NT, 0, st>>>(Bp, ldB, nao, Ct, rs, ncol, ncp, X, nib, nmb,
+                                                                     nblk);
+}
+
 // Compiled 16-bit GEMM1 tiles: (orbital columns, basis-function rows) per
 // workgroup; the first three stage both operands in LDS, the rest load A
 // straight into registers.
@@ -917,9 +1142,12 @@ struct G16Tile {
     int cols, rows;
 };
 constexpr G16Tile kG16Tiles[] = {{64, 128}, {128, 128}, {208, 128}, {128, 128}, {208, 128},
-                                 {128, 256}, {64, 256}, {416, 128}};
+                                 {128, 256}, {64, 256}, {416, 128}, {416, 128}, {256, 128},
+                                 {96, 64},   {64, 64},   {32, 64}};
 // 7: g1_w, 8 wavefronts, both operands staged in LDS, 416 columns, operand
-// reads scheduled ahead of the products
+// reads scheduled ahead of the products.  8 and up: g1_p on the packed
+// triangle (no dense copy of B).
+constexpr int kFirstPackedG16 = 8;
 constexpr int kNumG16Tiles = sizeof(kG16Tiles) / sizeof(kG16Tiles[0]);
 
 // Default tile: least padded orbital columns per unit of measured rate.  On
@@ -956,9 +1184,19 @@ inline int pick_g16_tile_16(int64_t ncp) {
     return best;
 }
 
+// Bd / ldd: the dense copy (tiles below kFirstPackedG16); Bp / ldB: the
+// packed triangle (tiles from kFirstPackedG16 on).
 template <typename H>
-void launch_g16(int t, hipStream_t st, const H* Bd, int64_t ldd, int64_t rs, int64_t nao, const H* Ct, int64_t ncol,
-                int64_t ncp, H* X, int64_t naux) {
+void launch_g16(int t, hipStream_t st, const H* Bd, int64_t ldd, const H* Bp, int64_t ldB, int64_t rs, int64_t nao,
+                const H* Ct, int64_t ncol, int64_t ncp, H* X, int64_t naux) {
+    switch (t) {
+        case 8: launch_gp<H, 4, 2, 2, 13>(st, Bp, ldB, nao, Ct, rs, ncol, ncp, X, naux); return;
+        case 9: launch_gp<H, 4, 2, 2, 8>(st, Bp, ldB, nao, Ct, rs, ncol, ncp, X, naux); return;
+        case 10: launch_gp<H, 2, 2, 2, 3>(st, Bp, ldB, nao, Ct, rs, ncol, ncp, X, naux); return;
+        case 11: launch_gp<H, 2, 2, 2, 2>(st, Bp, ldB, nao, Ct, rs, ncol, ncp, X, naux); return;
+        case 12: launch_gp<H, 2, 2, 2, 1>(st, Bp, ldB, nao, Ct, rs, ncol, ncp, X, naux); return;
+        default: break;
+    }
     switch (t) {
         case 0: launch_g1<H, 4>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
         case 1: launch_g1<H, 8>(st, Bd, ldd, rs, nao, Ct, ncol, ncp, X, naux); break;
@@ -1041,7 +1279,9 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     int rc;
     if ((rc = h->Cw.ensure(plan.Cw)) || (rc = h->X.ensure(plan.X)) || (rc = h->kpart.ensure(plan.kpart)))
         return rc;
-    if (!h->dense_ready && (rc = make_dense_t<H>(h))) return rc;
+    int t = h->k16_tile;
+    if (t < 0 || t >= kNumG16Tiles) t = pick_g16_tile(ncp);
+    if (t < kFirstPackedG16 && !h->dense_ready && (rc = make_dense_t<H>(h))) return rc;
     H* Ct = static_cast<H*>(h->Cw.ptr);
     H* X = static_cast<H*>(h->X.ptr);
     const H* Bd = static_cast<const H*>(h->Bdense.ptr);
@@ -1049,9 +1289,7 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     c_transpose<H><<<dim3((unsigned)cdiv(ncp * ldd, 256)), 256, 0, st>>>(C, nao, ncol, ncp, ldd, k16_rs(ldd), Ct);
     DFJK_LAUNCH_CHECK("c_transpose");
     h->prof.begin(PH_K_GEMM1, st);
-    int t = h->k16_tile;
-    if (t < 0 || t >= kNumG16Tiles) t = pick_g16_tile(ncp);
-    launch_g16<H>(t, st, Bd, ldd, k16_rs(ldd), nao, Ct, ncol, ncp, X, naux);
+    launch_g16<H>(t, st, Bd, ldd, static_cast<const H*>(h->B), h->ldB, k16_rs(ldd), nao, Ct, ncol, ncp, X, naux);
     h->prof.end(PH_K_GEMM1, st);
     DFJK_LAUNCH_CHECK("g1_16");
     const int64_t T = plan.T, ntl = plan.ntl, nsplit = plan.nsplit, pchunk = plan.pchunk;
@@ -1074,6 +1312,71 @@ int k16_t(dfjk_ctx* h, const double* C, int64_t ncol, double scale, double* K) {
     h->prof.end(PH_K_FINISH, st);
     h->prof.end(PH_K, st);
     DFJK_LAUNCH_CHECK("syrk16_finish");
+    return DFJK_OK;
+}
+
+// ---------------------------------------------------------------- batched
+// The 16-bit exchange over many molecules: every phase is one launch over
+// all molecules' blocks; a block finds its molecule by binary search in the
+// phase's prefix table (molecules longest first).
+__device__ inline int find_mol16(const int64_t* __restrict__ prefix, int n, int64_t b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename H>
+__global__ __launch_bounds__(kT) void kb16_kernel(int kind, const MolDesc* __restrict__ mols, PhaseList pl) {
+    const int64_t b = kind == BP_SYRK16 ? xcd_lid(blockIdx.x, pl.nblk) : (int64_t)blockIdx.x;
+    const int j = find_mol16(pl.prefix, pl.n, b);
+    const MolDesc& d = mols[pl.ids[j]];
+    const int64_t lid = b - pl.prefix[j];
+    if (kind == BP_CT16) {
+        const int64_t e = lid * kT + threadIdx.x;
+        if (e < d.ncp16 * d.ldd16) {
+            const int64_t i = e / d.ldd16, nu = e % d.ldd16;
+            const double v = (i < d.nocc && nu < d.nao) ? d.C[nu * d.nocc + i] : 0.0;
+            static_cast<H*>(d.Ct16)[i * d.rs16 + nu] = Mma16<H>::from_double(v);
+        }
+    } else if (kind == BP_SYRK16) {
+        syrk16_body<H>(lid, static_cast<const H*>(d.X16), d.nao, d.ncp16, d.naux, d.pchunk16, d.ntl, d.kpart16);
+    } else if (kind == BP_KFIN16) {
+        syrk16_finish_body<128>(lid, d.kpart16, d.nsplit16, d.ntl, d.nao, 2.0, d.K);
+    }
+}
+
+// GEMM1 of bucket FN - 1: 64 rows x 32 FN columns per workgroup, on the
+// packed triangle.
+template <typename H, int FN>
+__global__ __launch_bounds__(kT) void kb16_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
+    using G = G1P<2, 2, 2, FN>;
+    static_assert(G::NT == kT, "batched GEMM1 runs 256 threads");
+    const int64_t b = xcd_lid(blockIdx.x, pl.nblk);
+    const int j = find_mol16(pl.prefix, pl.n, b);
+    const MolDesc& d = mols[pl.ids[j]];
+    g1p_body<H, 2, 2, 2, FN>(b - pl.prefix[j], static_cast<const H*>(d.B), d.ldB, d.nao,
+                             static_cast<const H*>(d.Ct16), d.rs16, d.nocc, d.ncp16, static_cast<H*>(d.X16),
+                             cdiv(d.ncp16, G::BI), cdiv(d.nao, G::BM));
+}
+
+template <typename H>
+int k16_batch_phase_t(hipStream_t st, int kind, int bucket, const MolDesc* mols, const PhaseList& pl) {
+    const dim3 grid((unsigned)pl.nblk);
+    if (kind == BP_G16) {
+        switch (bucket) {
+            case 0: kb16_gemm1<H, 1><<<grid, kT, 0, st>>>(mols, pl); break;
+            case 1: kb16_gemm1<H, 2><<<grid, kT, 0, st>>>(mols, pl); break;
+            default: kb16_gemm1<H, 3><<<grid, kT, 0, st>>>(mols, pl); break;
+        }
+        DFJK_LAUNCH_CHECK("kb16_gemm1");
+    } else {
+        kb16_kernel<H><<<grid, kT, 0, st>>>(kind, mols, pl);
+        DFJK_LAUNCH_CHECK("kb16_kernel");
+    }
     return DFJK_OK;
 }
 
@@ -1121,6 +1424,48 @@ int k16_tile_info(int index, int* cols, int* rows) {
     *cols = kG16Tiles[index].cols;
     *rows = kG16Tiles[index].rows;
     return DFJK_OK;
+}
+
+// Batch geometry: C^T and X padded to 32 orbital columns; the GEMM2 split
+// gives every molecule at least 32 workgroups and no workgroup more than
+// about 1024 (P, i) terms (which also bounds its FP32 running sums).
+void k16_batch_geometry(MolDesc& d, size_t* ct_bytes, size_t* x_bytes, size_t* kpart_bytes) {
+    d.ldd16 = k16_ldd(d.nao);
+    d.rs16 = k16_rs(d.ldd16);
+    d.ncp16 = cdiv(d.nocc, KS) * KS;
+    int64_t pchunk = 1024 / d.ncp16;
+    const int64_t want = cdiv(32, d.ntl);
+    if (pchunk > cdiv(d.naux, want)) pchunk = cdiv(d.naux, want);
+    if (pchunk < 1) pchunk = 1;
+    d.pchunk16 = pchunk;
+    d.nsplit16 = cdiv(d.naux, pchunk);
+    *ct_bytes = 2 * (size_t)(d.ncp16 * d.rs16);
+    *x_bytes = 2 * (size_t)(d.naux * d.nao * d.ncp16);
+    *kpart_bytes = sizeof(float) * (size_t)(d.nsplit16 * d.ntl) * 128 * 128;
+}
+
+// GEMM1 buckets: 32, 64 and at least 96 padded orbital columns.
+int k16_batch_bucket(const MolDesc& d) {
+    const int64_t w = d.ncp16 / KS;
+    return (int)(w < 3 ? w : 3) - 1;
+}
+
+int64_t k16_batch_blocks(int kind, int bucket, const MolDesc& d) {
+    switch (kind) {
+        case BP_CT16: return cdiv(d.ncp16 * d.ldd16, kT);
+        case BP_G16: return cdiv(d.ncp16, (int64_t)KS * (bucket + 1)) * cdiv(d.nao, 64) * d.naux;
+        case BP_SYRK16: return d.ntl * d.nsplit16;
+        case BP_KFIN16: return d.ntl * kFin16;
+        default: return 0;
+    }
+}
+
+int k16_batch_phase(hipStream_t st, int kind, int bucket, int dtype, const MolDesc* mols, const PhaseList& pl) {
+    if (pl.nblk <= 0) return DFJK_OK;
+    if (dtype == DFJK_BF16) return k16_batch_phase_t<uint16_t>(st, kind, bucket, mols, pl);
+    if (dtype == DFJK_F16) return k16_batch_phase_t<_Float16>(st, kind, bucket, mols, pl);
+    set_error("16-bit exchange needs BF16 or FP16 B");
+    return DFJK_E_DTYPE;
 }
 
 }  // namespace dfjk

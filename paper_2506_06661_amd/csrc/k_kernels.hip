@@ -204,7 +204,7 @@ __device__ inline int64_t xcd_logical(int64_t hw, int64_t nblk) {
 // Columns [ioff, iend) of the ncol orbital columns (a launch may cover part of
 // them with one tile and the rest with another).
 template <typename T, typename TS, int NI, int WM>
-__device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
+__device__ __attribute__((always_inline)) inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                     T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb,
                                     int64_t ioff = 0, int64_t iend = -1) {
@@ -277,7 +277,7 @@ __device__ inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64
 typedef float v16f_k __attribute__((ext_vector_type(16)));
 
 template <typename TS, int NJ, int WJ>
-__device__ inline void k_gemm1w_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
+__device__ __attribute__((always_inline)) inline void k_gemm1w_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                      const float* __restrict__ C, int64_t ldc, int64_t ncol,
                                      float* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb,
                                      int64_t ioff = 0, int64_t iend = -1) {
@@ -402,7 +402,7 @@ __device__ inline void sy_load(SyStage<T>& st, const T* __restrict__ X, int64_t 
 // (k' = k, or the row paired with k for two factors); block id = s*ntl + t,
 // t a lower tile (I >= J) or, for SY_PAIR_FULL, any tile (I = t / nt)
 template <typename T, int MODE = SY_SYM>
-__device__ inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t ldx, int64_t nrows,
+__device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                    int64_t nao, int64_t ncol, const double* __restrict__ sign,
                                    int64_t kchunk, int64_t ntl, T* __restrict__ part, int64_t boff = 0) {
     // FP32 reads cover 4 rows x 16 columns over 64 banks: pitch 144 = 16 mod 64
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int6
 // K[mu][nu] = K[nu][mu] = scale * sum_s partial[s][t][m][n] over the lower
 // triangle (on diagonal tiles only m >= n is used, so K is exactly symmetric).
 template <typename T>
-__device__ inline void k_syrk_finish_body(int64_t t, int e0, int e1, const T* __restrict__ part,
+__device__ __attribute__((always_inline)) inline void k_syrk_finish_body(int64_t t, int e0, int e1, const T* __restrict__ part,
                                           int64_t nsplit, int64_t ntl, int64_t nao, double scale,
                                           double* __restrict__ K) {
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -599,9 +599,8 @@ struct G1Tile {
     }
 // Tiles 14..16: the FP32 32 x 32 x 2 form, (NI, WM) = (2 NJ, 2 WJ); no FP64
 // launcher (FP64 has no 32 x 32 step).  Not defaults: at nao=1024,
-// naux=4096, nocc=200 (FP32 B) on MI355X they took 28.8 / 48.2 / 38.9 ms
-// against 24.9 ms for (5,1): the shared staging code needs 200-248 VGPRs for
-// their wider tiles, leaving 1-2 wavefronts per SIMD.
+// naux=4096, nocc=200 (FP32 B) on MI355X they took 24.9 / 29.7 / 28.0 ms
+// against 21.5 ms for (13,1) on 16 x 16 x 4 steps.
 #define G1W(a, b)                                                                              \
     {                                                                                          \
         2 * a, 2 * b, {                                                                        \
@@ -629,14 +628,15 @@ __global__ void to_f32(const double* __restrict__ x, int64_t n, float* __restric
 // read of the B tile (weight 1/2 of a padded column block), among the tiles
 // that keep two waves per SIMD (FP64 sweep on MI355X, nao=1024, nocc=200:
 // (7,1) 43.8 TFLOP/s, (5,2) 43.5, (13,1) 40.4, (1,2) 32.6).
-// FP32 compute (FP32/BF16/FP16 storage) allows at most 5 accumulator tiles
-// (sweep at nocc=200: (5,1) 66.2 TFLOP/s, (7,1) 63.1, (4,2) 59.1, (1,2) 50.3).
+// FP32 compute (FP32/BF16/FP16 storage) allows up to 14 accumulator tiles
+// (sweep at nocc=200, FP32 B: (13,1) and (7,2) 79.7 TFLOP/s, (5,2) 76.6,
+// (7,1) 76.0, (5,1) 68.7, (8,2) 72.5, (4,4) 62.5).
 int pick_g1_tile(int64_t ncol, bool f32 = false) {
     int best = 0;
     double best_cost = 1e300;
     for (int t = 0; t < kFirstRestTile; ++t) {
         const int ni = kG1Tiles[t].ni, wm = kG1Tiles[t].wm;
-        if (ni * wm > (f32 ? 5 : 7)) continue;  // larger accumulator sets leave one wave per SIMD
+        if (ni * wm > (f32 ? 14 : 7)) continue;  // larger accumulator sets leave one wave per SIMD
         const double padded = (double)(cdiv(ncol, 16 * ni) * 16 * ni);
         const double cost = padded * (1.0 + 0.5 / ni);
         if (cost < best_cost) {

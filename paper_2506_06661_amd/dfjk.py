@@ -89,6 +89,7 @@ def lib():
         L.dfjk_batch_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(dbl)]
         L.dfjk_batch_get_tile.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.dfjk_batch_set_tile.argtypes = [vp, i32, i32]
+        L.dfjk_batch_set_k16.argtypes = [vp, i32]
         L.dfjk_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.dfjk_batch_destroy.argtypes = [vp]
         L.dfjk_batch_destroy.restype = None
@@ -99,7 +100,7 @@ def lib():
             getattr(L, name).restype = i32
         for name in ("dfjk_batch_init", "dfjk_batch_build", "dfjk_batch_capture", "dfjk_batch_launch",
                      "dfjk_batch_autotune", "dfjk_batch_get_tile", "dfjk_batch_set_tile",
-                     "dfjk_batch_workspace_bytes"):
+                     "dfjk_batch_set_k16", "dfjk_batch_workspace_bytes"):
             getattr(L, name).restype = i32
         L.dfjk_mlp_init.argtypes = [ctypes.POINTER(vp), i32, i32, i64, vp]
         L.dfjk_mlp_nparam.argtypes = [vp]
@@ -326,6 +327,10 @@ class Batch:
 
     def set_tile(self, bucket: int, tile: int):
         return _check("dfjk_batch_set_tile", lib().dfjk_batch_set_tile(self.h, bucket, tile))
+
+    def set_k16(self, on: bool = True):
+        """Exchange on the 16-bit matrix cores (BF16 / FP16 B only)."""
+        return _check("dfjk_batch_set_k16", lib().dfjk_batch_set_k16(self.h, int(bool(on))))
 
     def _hlist(self, H_list):
         if len(H_list) != len(self.mols):

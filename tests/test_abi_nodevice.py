@@ -85,6 +85,7 @@ def test_batch_invalid_arguments(L):
     assert "molecule 0" in pkg.dfjk_last_error()
     assert L.dfjk_batch_build(None) == -1
     assert L.dfjk_batch_launch(None) == -1
+    assert L.dfjk_batch_set_k16(None, 1) == -1
     L.dfjk_batch_destroy(None)
 
 

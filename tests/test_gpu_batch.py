@@ -128,3 +128,53 @@ def test_autotune_keeps_parity(pkg, tmp_path, dtype):
     torch.cuda.synchronize()
     _check_all(mols2, refs, "cached tiles")
     bt2.close()
+
+
+@pytest.mark.parametrize("dtype,bound", [(2, 2 * 2.0 ** -8 + 5e-4), (3, 2 * 2.0 ** -11 + 5e-4)])
+def test_batch_k16_matches_oracle(pkg, dtype, bound):
+    """Exchange on the 16-bit matrix cores over the batch (GEMM1 on the packed
+    triangle, buckets of 32, 64 and 96 padded orbital columns, all present
+    here).  Reference: the oracle on the stored B with C rounded once to the
+    same format; bound as for the single-molecule 16-bit exchange (X rounded
+    to 16 bits: |dK| <= 2u max|K| to first order, FP32 sums < 5e-4).  J is
+    the FP64-accumulated one (1e-10).  Graph replays equal the eager build
+    bit for bit; switching back gives the FP32 exchange's K bit for bit."""
+    sizes = [40, 97, 130, 41, 256, 72, 150, 64, 33, 200, 345, 400]
+    print(f"batch k16 dtype={dtype} sizes={sizes}", flush=True)
+    bt, mols, refs = make_batch(pkg, sizes, dtype, 4100)
+    bt.build()
+    torch.cuda.synchronize()
+    k32 = [host(m["K"]).copy() for m in mols]
+    bt.set_k16(True)
+    bt.build()
+    torch.cuda.synchronize()
+    for m, (Bq, C, D) in zip(mols, refs):
+        nao = m["nao"]
+        K = host(m["K"])
+        err = max_rel(K, oracle.K_C(Bq, nao, QUANT[dtype](C)))
+        assert err < bound, (nao, err)
+        assert np.array_equal(K, K.T), nao
+        assert max_rel(host(m["J"]), oracle.J(Bq, nao, D)) < 1e-10, nao
+    eager = [host(m["K"]).copy() for m in mols]
+    bt.capture()
+    for rep in range(2):
+        for m in mols:
+            m["K"].zero_()
+        torch.cuda.synchronize()
+        bt.launch()
+        torch.cuda.synchronize()
+        for m, K0 in zip(mols, eager):
+            assert np.array_equal(host(m["K"]), K0), rep
+    bt.set_k16(False)
+    bt.build()
+    torch.cuda.synchronize()
+    for m, K0 in zip(mols, k32):
+        assert np.array_equal(host(m["K"]), K0)
+    bt.close()
+
+
+def test_batch_k16_needs_16bit_storage(pkg):
+    bt, _, _ = make_batch(pkg, [40, 60], 1, 4400)
+    with pytest.raises(RuntimeError, match="16-bit exchange"):
+        bt.set_k16(True)
+    bt.close()

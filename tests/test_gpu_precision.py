@@ -14,7 +14,8 @@
       (SYRK), split partials added in FP64: |dK| <= ~(nao + kchunk) u32 *
       sum|X||X|; asserted at 2e-4 of the largest entry.
 * Against the FP64 oracle on the FP64 B the error is dominated by the
-  storage rounding of B (u = 2^-24, 2^-9, 2^-12); it is reported.
+  storage rounding of B (unit roundoff u = 2^-24, 2^-8, 2^-11 for FP32,
+  BF16, FP16); it is reported.
 """
 import numpy as np
 import pytest
