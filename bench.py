@@ -137,6 +137,105 @@ def counter_traffic(workload: str):
     return info["traffic_bytes"]
 
 
+TRAFFIC_SOURCES = ("k_kernels.hip", "j_kernels.hip", "mma.h")
+
+
+def traffic_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
+                    first: int, command: str) -> str:
+    """Markdown summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE
+    in KiB per dispatch) of the default nao=1024 FP64 workload, scaled by
+    what the same counters read for a 1 GiB device copy (--copy-calibration).
+    Per kernel: the mean over its first `first` dispatches (the warm-up and
+    timed steps; later dispatches of the same kernel belong to the extra
+    measurements).  The JSON block is what counter_traffic reads."""
+    import collections
+    import csv
+    import hashlib
+    import re
+
+    def per_dispatch(d, counter):
+        path = os.path.join(d, "run_counter_collection.csv")
+        vals = collections.OrderedDict()
+        names = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = int(r["Dispatch_Id"])
+            vals[k] = vals.get(k, 0.0) + float(r["Counter_Value"])
+            m = re.search(r"(\w+)(<[^()]*>)?\(", r["Kernel_Name"])
+            names[k] = (m.group(1) + (m.group(2) or "")) if m else r["Kernel_Name"][:60]
+        out = collections.OrderedDict()
+        for k in sorted(vals):
+            out.setdefault(names[k], []).append(vals[k])
+        return out
+
+    gib = float(1 << 30)
+    cf = per_dispatch(copy_fetch_dir, "FETCH_SIZE")
+    cw = per_dispatch(copy_write_dir, "WRITE_SIZE")
+    ck = [k for k in cf if "copyBuffer" in k][0]
+    f_scale = gib / (float(np.median(cf[ck])) * 1024.0)
+    w_scale = gib / (float(np.median(cw[ck])) * 1024.0)
+    fe = per_dispatch(fetch_dir, "FETCH_SIZE")
+    wr = per_dispatch(write_dir, "WRITE_SIZE")
+    cfg = __import__("synth").C2
+    npair = cfg.nao * (cfg.nao + 1) // 2
+    b_bytes = cfg.naux * npair * 8.0
+    x_bytes = cfg.naux * cfg.nocc * cfg.nao * 8.0
+    mins = {"j_rho_f64": b_bytes, "j_out_f64": b_bytes, "k_syrk_f64": x_bytes}
+    rows, traffic = [], {}
+    g1_total = 0.0
+    for name, fv in fe.items():
+        if name not in wr or name.startswith(("at::", "void at::")) or "rocclr" in name:
+            continue
+        f_kib = float(np.mean(fv[:first]))
+        w_kib = float(np.mean(wr[name][:first]))
+        byts = f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale
+        key = None
+        if name.startswith("k_gemm1<double"):
+            g1_total += byts
+            key = "k_gemm1_f64 launch " + name
+        elif name.startswith("j_rho_f64<"):
+            key = "j_rho_f64"
+        elif name.startswith("j_out_f64<") and name.endswith("false>"):
+            key = "j_out_f64"
+        elif name == "k_syrk<double, 0>":
+            key = "k_syrk_f64"
+        mn = mins.get(key)
+        rows.append(f"| `{name}` | {f_kib:.4g} | {w_kib:.4g} | {byts:.4g} | "
+                    f"{'%.4g' % mn if mn else ''} | {'%.3f' % (byts / mn) if mn else ''} |")
+        traffic[key or name] = byts
+    traffic["k_gemm1_f64"] = g1_total
+    g1_min = b_bytes + x_bytes
+    digests = {src: hashlib.sha256(open(os.path.join(ROOT, "paper_2506_06661_amd", "csrc", src), "rb").read())
+               .hexdigest()[:16] for src in TRAFFIC_SOURCES}
+    info = {"workload": "c2-f64", "sources": digests, "traffic_bytes": traffic}
+    lines = [
+        f"# HBM traffic per launch: DF J/K build, nao={cfg.nao} naux={cfg.naux} nocc={cfg.nocc}, FP64 B (MI355X)",
+        "",
+        "Commands (from the repository root; one counter per run), then this summary:",
+        "",
+        "```", command, "```", "",
+        f"Calibration: a 1 GiB device copy (`{ck}`) reads FETCH_SIZE = {np.median(cf[ck]):.0f} KiB and "
+        f"WRITE_SIZE = {np.median(cw[ck]):.0f} KiB,",
+        f"so FETCH_SIZE is scaled by {f_scale:.3f} and WRITE_SIZE by {w_scale:.3f} to give bytes. Values are "
+        f"the mean over each kernel's first {first} dispatches (warm-up and timed steps).",
+        "",
+        "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM bytes | minimum algorithmic bytes | ratio |",
+        "|---|---|---|---|---|---|",
+        *rows,
+        "",
+        "Minimum algorithmic bytes: each J pass reads B once (naux*npair*8); the GEMM1 phase reads B once and "
+        "writes X (naux*nocc*nao*8); the SYRK reads X once.",
+        f"GEMM1 phase (all launches of a step): {g1_total:.4g} bytes against a minimum of {g1_min:.4g} "
+        f"({g1_total / g1_min:.2f}x): each launch reads every packed element for both triangles it serves.",
+        "",
+        "Machine-readable (read by bench.py while the kernel sources are unchanged):",
+        "",
+        "```json", json.dumps(info), "```", "",
+    ]
+    return "\n".join(lines)
+
+
 def time_steps(pkg, h, Dd, Cd, cfg, steps, warmup):
     """Per-phase event averages over `steps` J+K steps on handle h."""
     import torch
@@ -695,9 +794,19 @@ def main():
                     help="c5: scale of B in the SCF family (default: the generator's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                           "COPY_WRITE_DIR"),
+                    help="print the HBM traffic summary of four rocprofv3 --pmc output folders (no GPU)")
+    ap.add_argument("--traffic-first", type=int, default=3,
+                    help="dispatches per kernel that belong to the warm-up and timed steps")
+    ap.add_argument("--traffic-command", default="",
+                    help="the rocprofv3 commands, quoted into the summary")
     ap.add_argument("--cpu-rows", type=int, default=512,
                     help="aux rows in the CPU-oracle sample (0 = skip)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(traffic_summary(*args.traffic_summary, args.traffic_first, args.traffic_command))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
