@@ -350,7 +350,7 @@ int dfjk_batch_init(dfjk_batch* out, const dfjk_mol* mols, int nmol, int dtype, 
         d.C = m.Cocc;
         d.J = m.J;
         d.K = m.K;
-        d.vec = (m.ldB % V == 0) && ((reinterpret_cast<uintptr_t>(m.B) & 15) == 0) ? 1 : 0;
+        d.vec = 1;  // 16-byte loads of B at any element alignment
         (void)esz;
         const int64_t rowblocks = cdiv(d.naux, 8);
         int64_t chunks = cdiv(64, rowblocks);

@@ -262,10 +262,13 @@ struct Elem<_Float16> {
     __device__ static float f(_Float16 x) { return (float)x; }
 };
 
+// 16 bytes of B from any element-aligned address (the rows of a packed B
+// with ldB not a multiple of V start at any element; the GPU's global loads
+// take unaligned addresses).
 template <typename TB>
 __device__ inline void load16(const TB* p, float* out) {
     constexpr int V = Elem<TB>::V;
-    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u4 __attribute__((ext_vector_type(4), aligned(2)));
     const u4 raw = __builtin_nontemporal_load(reinterpret_cast<const u4*>(p));
     const TB* e = reinterpret_cast<const TB*>(&raw);
 #pragma unroll
@@ -319,7 +322,7 @@ __device__ __attribute__((always_inline)) inline void j_rho_red_body(int64_t bx,
     Acc<ACC> acc[R];
     int64_t p = c0;
     if (vec) {
-        // c0 is a multiple of V and rows are 16-byte aligned
+        // c0 is a multiple of V; rows may start at any element
         for (p = c0 + (int64_t)V * threadIdx.x; p + V <= c1; p += (int64_t)V * kThreads) {
             double m[V];
             float mh[V], ml[V];
@@ -452,7 +455,7 @@ int j_build_red_t(dfjk_ctx* h, double* J, double* rho_out, double* diag) {
         split_f64<<<dim3((unsigned)cdiv(h->npair, 256)), 256, 0, st>>>(dt, h->npair, dhi, dlo);
         DFJK_LAUNCH_CHECK("split_f64");
     }
-    const bool vec = (h->ldB % V == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
+    const bool vec = true;  // 16-byte loads at any element alignment (load16)
     int64_t chunk = cdiv(h->npair, h->j_chunks);
     chunk = cdiv(chunk, V) * V;
     const dim3 g1((unsigned)cdiv(h->naux, R), (unsigned)h->j_chunks);

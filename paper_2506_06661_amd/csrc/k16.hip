@@ -771,8 +771,8 @@ __device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, cons
                                 H* __restrict__ X, int64_t nib, int64_t nmb) {
     using G = G1P<WM, WN, FM, FN>;
     constexpr int BM = G::BM, BI = G::BI, NT = G::NT, PB = G::PB, PC = G::PC, OCT = BM / 8;
-    __shared__ uint16_t sA[2][BM][KCP];
-    __shared__ uint16_t sC[2][BI][KCP];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM][KCP];
+    __shared__ __attribute__((aligned(16))) uint16_t sC[2][BI][KCP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
     const int64_t ib = lid % nib, mb = (lid / nib) % nmb, P = lid / (nib * nmb);
@@ -822,6 +822,28 @@ __device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, cons
                 __builtin_memcpy(&sb[2 * u], Bw + t0 + mu0 + 8 * o, 16);
                 __builtin_memcpy(&sb[2 * u + 1], Bw + t1 + mu0 + 8 * o, 16);
             }
+        } else if constexpr (BM == KCP) {
+            // the diagonal block (nu0 == mu0): its lower triangle from the packed
+            // rows (whole pieces as 16-byte loads, the piece holding the
+            // diagonal element by element); the upper part is mirrored in LDS
+            // after the store
+#pragma unroll
+            for (int j = 0; j < PB; ++j) {
+                const int e = tid + j * NT;
+                const int64_t mu = mu0 + (e >> 3), nb = nu0 + 8 * (e & 7);
+                if (mu < nao && nb + 7 <= mu) {
+                    __builtin_memcpy(&sb[j], Bw + trow[j] + nb, 16);
+                } else {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int t = 0; t < 8; t += 2) {
+                        const uint32_t lo = (mu < nao && nb + t <= mu) ? (uint32_t)Bw[trow[j] + nb + t] : 0u;
+                        const uint32_t hi = (mu < nao && nb + t + 1 <= mu) ? (uint32_t)Bw[trow[j] + nb + t + 1] : 0u;
+                        w[t >> 1] = lo | (hi << 16);
+                    }
+                    sb[j] = u4{w[0], w[1], w[2], w[3]};
+                }
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < PB; ++j) {
@@ -870,6 +892,17 @@ __device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, cons
                 const int e = tid + j * NT, r = e >> 3;
                 *reinterpret_cast<u4*>(&sA[buf][r][swzp(r, e & 7)]) = (!bl || rok[j]) ? sb[j] : z4;
             }
+            if constexpr (BM == KCP) {
+                if (!bl) {
+                    // diagonal block: B[mu][nu] = B[nu][mu] above the diagonal
+                    __syncthreads();
+#pragma unroll 1
+                    for (int k = 0; k < KCP * KCP / NT; ++k) {
+                        const int e = tid + k * NT, r = e / KCP, c = e % KCP;
+                        if (c > r) sA[buf][r][swzp(r, c >> 3) + (c & 7)] = sA[buf][c][swzp(c, r >> 3) + (r & 7)];
+                    }
+                }
+            }
         }
     };
     v4f acc[FM][FN];
@@ -878,13 +911,7 @@ __device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, cons
 #pragma unroll
         for (int b = 0; b < FN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
     const int64_t nk = cdiv(nao, KCP);  // Ct holds zeros from nao to the next multiple of 64
-    load(0);
-    store(0, 0);
-    __syncthreads();
-    for (int64_t kc = 0; kc < nk; ++kc) {
-        const int buf = kc & 1;
-        const bool more = kc + 1 < nk;
-        if (more) load((kc + 1) * KCP);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < KCP / KS; ++ks) {
             const int pc = ks * (KS / 8) + (lane >> 4);
@@ -918,20 +945,53 @@ __device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, cons
                 __builtin_amdgcn_sched_group_barrier(0x008, FM * FN - FM * (NR - R0), 0);
             }
         }
-        if (more) store(buf ^ 1, (kc + 1) * KCP);
+    };
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const bool more = kc + 1 < nk;
+        if (more) load((kc + 1) * KCP);
+        compute(kc & 1);
+        if (more) store((kc & 1) ^ 1, (kc + 1) * KCP);
         __syncthreads();
     }
+    if constexpr (BM * BI <= 2 * BM * KCP) {
+        // the output tile through LDS (free after the last barrier), then
+        // written as 16-byte pieces of the X rows
+        uint16_t* sO = &sA[0][0][0];
 #pragma unroll
-    for (int f = 0; f < FM; ++f)
+        for (int f = 0; f < FM; ++f)
 #pragma unroll
-        for (int n = 0; n < FN; ++n)
+            for (int n = 0; n < FN; ++n)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t mu = mu0 + wm * 16 * FM + f * 16 + 4 * (lane >> 4) + r;
-                const int64_t i = i0 + wn * 16 * FN + n * 16 + (lane & 15);
-                if (mu < nao && i < ncp)
-                    X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[f][n][r] : 0.f);
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wm * 16 * FM + f * 16 + 4 * (lane >> 4) + r;
+                    const int col = wn * 16 * FN + n * 16 + (lane & 15);
+                    const H v = Mma16<H>::from_float(i0 + col < ncol ? acc[f][n][r] : 0.f);
+                    __builtin_memcpy(&sO[row * BI + col], &v, 2);
+                }
+        __syncthreads();
+#pragma unroll
+        for (int e = tid; e < BM * BI / 8; e += NT) {
+            const int row = e / (BI / 8), pc = e % (BI / 8);
+            const int64_t mu = mu0 + row, i = i0 + 8 * pc;
+            if (mu < nao && i < ncp)
+                *reinterpret_cast<u4*>(&X[(P * nao + mu) * ncp + i]) = *reinterpret_cast<const u4*>(&sO[row * BI + 8 * pc]);
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < FM; ++f)
+#pragma unroll
+            for (int n = 0; n < FN; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t mu = mu0 + wm * 16 * FM + f * 16 + 4 * (lane >> 4) + r;
+                    const int64_t i = i0 + wn * 16 * FN + n * 16 + (lane & 15);
+                    if (mu < nao && i < ncp)
+                        X[(P * nao + mu) * ncp + i] = Mma16<H>::from_float(i < ncol ? acc[f][n][r] : 0.f);
+                }
+    }
 }
 
 template <typename H, int WM, int WN, int FM, int FN>
@@ -1352,7 +1412,7 @@ __global__ __launch_bounds__(kT) void kb16_kernel(int kind, const MolDesc* __res
 // GEMM1 of bucket FN - 1: 64 rows x 32 FN columns per workgroup, on the
 // packed triangle.
 template <typename H, int FN>
-__global__ __launch_bounds__(kT) void kb16_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
+__global__ __launch_bounds__(kT, 4) void kb16_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
     using G = G1P<2, 2, 2, FN>;
     static_assert(G::NT == kT, "batched GEMM1 runs 256 threads");
     const int64_t b = xcd_lid(blockIdx.x, pl.nblk);
@@ -1428,12 +1488,15 @@ int k16_tile_info(int index, int* cols, int* rows) {
 
 // Batch geometry: C^T and X padded to 32 orbital columns; the GEMM2 split
 // gives every molecule at least 32 workgroups and no workgroup more than
-// about 1024 (P, i) terms (which also bounds its FP32 running sums).
+// about kBatch16SyrkTerms (P, i) terms (which also bounds its FP32 running
+// sums).  Every workgroup writes a 64 KB partial tile, so fewer, longer
+// splits save partial traffic.
+constexpr int64_t kBatch16SyrkTerms = 4096;
 void k16_batch_geometry(MolDesc& d, size_t* ct_bytes, size_t* x_bytes, size_t* kpart_bytes) {
     d.ldd16 = k16_ldd(d.nao);
     d.rs16 = k16_rs(d.ldd16);
     d.ncp16 = cdiv(d.nocc, KS) * KS;
-    int64_t pchunk = 1024 / d.ncp16;
+    int64_t pchunk = kBatch16SyrkTerms / d.ncp16;
     const int64_t want = cdiv(32, d.ntl);
     if (pchunk > cdiv(d.naux, want)) pchunk = cdiv(d.naux, want);
     if (pchunk < 1) pchunk = 1;
