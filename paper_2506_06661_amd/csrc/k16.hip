@@ -1409,18 +1409,18 @@ __global__ __launch_bounds__(kT) void kb16_kernel(int kind, const MolDesc* __res
     }
 }
 
-// GEMM1 of bucket FN - 1: 64 rows x 32 FN columns per workgroup, on the
-// packed triangle.
+// GEMM1 of bucket FN - 1: 32 kG16WM rows x 32 FN columns per workgroup,
+// on the packed triangle.
+constexpr int kG16WM = 2;
 template <typename H, int FN>
-__global__ __launch_bounds__(kT, 4) void kb16_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
-    using G = G1P<2, 2, 2, FN>;
-    static_assert(G::NT == kT, "batched GEMM1 runs 256 threads");
+__global__ __launch_bounds__(128 * kG16WM, 4) void kb16_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
+    using G = G1P<kG16WM, 2, 2, FN>;
     const int64_t b = xcd_lid(blockIdx.x, pl.nblk);
     const int j = find_mol16(pl.prefix, pl.n, b);
     const MolDesc& d = mols[pl.ids[j]];
-    g1p_body<H, 2, 2, 2, FN>(b - pl.prefix[j], static_cast<const H*>(d.B), d.ldB, d.nao,
-                             static_cast<const H*>(d.Ct16), d.rs16, d.nocc, d.ncp16, static_cast<H*>(d.X16),
-                             cdiv(d.ncp16, G::BI), cdiv(d.nao, G::BM));
+    g1p_body<H, kG16WM, 2, 2, FN>(b - pl.prefix[j], static_cast<const H*>(d.B), d.ldB, d.nao,
+                                  static_cast<const H*>(d.Ct16), d.rs16, d.nocc, d.ncp16,
+                                  static_cast<H*>(d.X16), cdiv(d.ncp16, G::BI), cdiv(d.nao, G::BM));
 }
 
 template <typename H>
@@ -1428,9 +1428,9 @@ int k16_batch_phase_t(hipStream_t st, int kind, int bucket, const MolDesc* mols,
     const dim3 grid((unsigned)pl.nblk);
     if (kind == BP_G16) {
         switch (bucket) {
-            case 0: kb16_gemm1<H, 1><<<grid, kT, 0, st>>>(mols, pl); break;
-            case 1: kb16_gemm1<H, 2><<<grid, kT, 0, st>>>(mols, pl); break;
-            default: kb16_gemm1<H, 3><<<grid, kT, 0, st>>>(mols, pl); break;
+            case 0: kb16_gemm1<H, 1><<<grid, 128 * kG16WM, 0, st>>>(mols, pl); break;
+            case 1: kb16_gemm1<H, 2><<<grid, 128 * kG16WM, 0, st>>>(mols, pl); break;
+            default: kb16_gemm1<H, 3><<<grid, 128 * kG16WM, 0, st>>>(mols, pl); break;
         }
         DFJK_LAUNCH_CHECK("kb16_gemm1");
     } else {
@@ -1516,7 +1516,7 @@ int k16_batch_bucket(const MolDesc& d) {
 int64_t k16_batch_blocks(int kind, int bucket, const MolDesc& d) {
     switch (kind) {
         case BP_CT16: return cdiv(d.ncp16 * d.ldd16, kT);
-        case BP_G16: return cdiv(d.ncp16, (int64_t)KS * (bucket + 1)) * cdiv(d.nao, 64) * d.naux;
+        case BP_G16: return cdiv(d.ncp16, (int64_t)KS * (bucket + 1)) * cdiv(d.nao, 32 * kG16WM) * d.naux;
         case BP_SYRK16: return d.ntl * d.nsplit16;
         case BP_KFIN16: return d.ntl * kFin16;
         default: return 0;
