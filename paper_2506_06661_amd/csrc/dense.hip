@@ -73,6 +73,108 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
             }
 }
 
+// C = alpha A B + beta C for large row-major FP64 products (no transposes):
+// 128 x 128 tile per workgroup, 2 x 2 waves of 64 x 64 (4 x 4 steps of
+// 16 x 16 x 4 per wavefront, the accumulators in the matrix-core registers),
+// K in 16-deep chunks double-buffered in LDS with the next chunk loaded into
+// registers while the current one is multiplied.  Loads are pairs of
+// doubles (rows start 16-byte aligned when lda, ldb are even and A, B are
+// 16-byte aligned; otherwise element loads).  The k order of every sum is
+// that of gemm_kernel (4-deep steps in increasing k), so both give the same
+// bits.
+constexpr int WT = 128, WK = 16;
+template <bool PAIRS>
+__global__ __launch_bounds__(256, 2) void gemm_nn_wide(int64_t M, int64_t N, int64_t K, double alpha,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ B, int64_t ldb, double beta,
+                                                        double* __restrict__ C, int64_t ldc) {
+    __shared__ double sA[2][WK][WT + 2];  // sA[k][m] = A[m0 + m][k0 + k]
+    __shared__ double sB[2][WK][WT + 2];  // sB[k][n] = B[k0 + k][n0 + n]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.y * WT, n0 = (int64_t)blockIdx.x * WT;
+    // thread's pairs: A rows m0 + tid/8 + 32 j at k pair 2 (tid%8); B rows
+    // tid/64 + 4 j at n pair 2 (tid%64)
+    const int am = tid >> 3, akp = 2 * (tid & 7), bk = tid >> 6, bnp = 2 * (tid & 63);
+    const bool full_mn = m0 + WT <= M && n0 + WT <= N;
+    double ra[4][2], rb[4][2];
+    auto load = [&](int64_t k0) {
+        if (PAIRS && full_mn && k0 + WK <= K) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const double2 va = *reinterpret_cast<const double2*>(A + (m0 + am + 32 * j) * lda + k0 + akp);
+                const double2 vb = *reinterpret_cast<const double2*>(B + (k0 + bk + 4 * j) * ldb + n0 + bnp);
+                ra[j][0] = va.x;
+                ra[j][1] = va.y;
+                rb[j][0] = vb.x;
+                rb[j][1] = vb.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const int64_t gm = m0 + am + 32 * j, gk = k0 + akp + d;
+                    ra[j][d] = (gm < M && gk < K) ? A[gm * lda + gk] : 0.0;
+                    const int64_t gkb = k0 + bk + 4 * j, gn = n0 + bnp + d;
+                    rb[j][d] = (gkb < K && gn < N) ? B[gkb * ldb + gn] : 0.0;
+                }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sA[buf][akp][am + 32 * j] = ra[j][0];
+            sA[buf][akp + 1][am + 32 * j] = ra[j][1];
+            sB[buf][bk + 4 * j][bnp] = rb[j][0];
+            sB[buf][bk + 4 * j][bnp + 1] = rb[j][1];
+        }
+    };
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t nk = cdiv(K, WK);
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int64_t kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        const bool more = kc + 1 < nk;
+        if (more) load((kc + 1) * WK);
+#pragma unroll
+        for (int kk = 0; kk < WK / 4; ++kk) {
+            const int kr = kk * 4 + (lane >> 4);
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = sA[buf][kr][wm * 64 + q * 16 + (lane & 15)];
+                b[q] = sB[buf][kr][wn * 64 + q * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = Mma<double>::step(a[ti], b[tj], acc[ti][tj]);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gm = m0 + wm * 64 + ti * 16 + Mma<double>::row(lane, r);
+                const int64_t gn = n0 + wn * 64 + tj * 16 + (lane & 15);
+                if (gm < M && gn < N) {
+                    const double old = beta == 0.0 ? 0.0 : beta * C[gm * ldc + gn];
+                    C[gm * ldc + gn] = alpha * acc[ti][tj][r] + old;
+                }
+            }
+}
+
 // C = op(A) op(B) with FP32 operands rounded once to bfloat16 (RNE) as they
 // are staged, products on v_mfma_f32_16x16x32_bf16, FP32 accumulation and
 // output.  64 x 64 tile per workgroup, 2 x 2 waves of 32 x 32 (2 x 2 steps of
@@ -378,6 +480,17 @@ int gemm_t(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, T 
 int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
           int64_t ldc) {
+    if (!ta && !tb && M >= WT && N >= WT && K >= WK) {
+        const dim3 grid((unsigned)cdiv(N, WT), (unsigned)cdiv(M, WT));
+        const bool pairs = lda % 2 == 0 && ldb % 2 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                           (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+        if (pairs)
+            gemm_nn_wide<true><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+        else
+            gemm_nn_wide<false><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+        DFJK_LAUNCH_CHECK("gemm_nn_wide");
+        return DFJK_OK;
+    }
     return gemm_t<double>(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
