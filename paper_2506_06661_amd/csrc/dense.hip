@@ -80,8 +80,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 // registers while the current one is multiplied.  Loads are pairs of
 // doubles (rows start 16-byte aligned when lda, ldb are even and A, B are
 // 16-byte aligned; otherwise element loads).  The k order of every sum is
-// that of gemm_kernel (4-deep steps in increasing k), so both give the same
-// bits.
+// that of gemm_kernel (4-deep steps in increasing k).
 constexpr int WT = 128, WK = 16;
 template <bool PAIRS>
 __global__ __launch_bounds__(256, 2) void gemm_nn_wide(int64_t M, int64_t N, int64_t K, double alpha,
