@@ -1009,6 +1009,22 @@ def main():
             "ms": kp_ms, "tflops": kp_flops / kp_ms / 1e9, "gemm1_ms": kp_g1, "gemm1_tflops": 2 * g1_flops / kp_g1 / 1e9,
             "gemm2_ms": kp_sy, "gemm2_tflops": 2 * sy_flops / kp_sy / 1e9, "ratio_to_k_occ": kp_ms / k_ms}
         del Ld, Rd, Kp
+        # K of a general (here indefinite) density at this size: the two
+        # factors (D, I), one call after a warm-up
+        A = torch.from_numpy(synth.C_occ(cfg.seed + 1, cfg.nao, cfg.nao)).cuda()
+        Dg = (A + A.T).contiguous()
+        Kg = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
+        pkg.dfjk_build_K(h.h, None, 0, Dg, Kg)
+        torch.cuda.synchronize()
+        e0.record()
+        pkg.dfjk_build_K(h.h, None, 0, Dg, Kg)
+        e1.record()
+        torch.cuda.synchronize()
+        kd_ms = e0.elapsed_time(e1)
+        kd_flops = 2 * 2.0 * cfg.naux * cfg.nao ** 3 + 2.0 * cfg.naux * cfg.nao * cfg.nao * (cfg.nao + 1)
+        res["k_from_density"] = {"ms": kd_ms, "tflops": kd_flops / kd_ms / 1e9, "ratio_to_k_occ": kd_ms / k_ms,
+                                 "form": "two factors (D, I): sum_P B_P D B_P"}
+        del A, Dg, Kg
     res["measured_mfma_ceiling_tflops"] = {
         "f64_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F64), "f32_16x16x4": pkg.dfjk_probe_mfma(pkg.DFJK_F32),
         "bf16_32x32x16": pkg.dfjk_probe_mfma(pkg.DFJK_BF16)}

@@ -38,6 +38,11 @@ __global__ void antisym_kernel(const double* __restrict__ G, int64_t n, double* 
     e[i] = G[r * n + c] - G[c * n + r];
 }
 
+__global__ void identity_kernel(int64_t n, double* __restrict__ Y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n * n) Y[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
 __global__ void symmetrize_kernel(const double* __restrict__ X, int64_t n, double* __restrict__ Y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * n) return;
@@ -274,6 +279,10 @@ static int scf_ws(dfjk_ctx* h, bool scf, ScfWs& ws) {
     return DFJK_OK;
 }
 
+// From this nao on, K of a density goes through the two factors (D, I)
+// instead of D's eigen-factors.
+constexpr int64_t kPairFromD = 256;
+
 int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
     const int64_t n = h->nao;
     h->scf_v_warm = false;  // the eigensolver buffer is reused below
@@ -288,6 +297,14 @@ int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
     const hipStream_t st = h->stream;
     symmetrize_kernel<<<dim3((unsigned)cdiv(n * n, 256)), 256, 0, st>>>(D, n, ws.A);
     DFJK_LAUNCH_CHECK("symmetrize_kernel");
+    if (n >= kPairFromD) {
+        // K = 1/2 sum_P [(B_P D)(B_P I)^T + (B_P I)(B_P D)^T]: two factors of
+        // nao columns each, no eigensolver (whose one-workgroup sweeps take
+        // seconds from nao ~ 500 on)
+        identity_kernel<<<dim3((unsigned)cdiv(n * n, 256)), 256, 0, st>>>(n, ws.V);
+        DFJK_LAUNCH_CHECK("identity_kernel");
+        return k_build_pair(h, ws.A, ws.V, n, 1, 0.5, K);
+    }
     if ((rc = eigh(st, ws.A, ws.V, (int)n, true, ws.work, ws.iwork, ws.w))) return rc;
     // D = sum_c w_c v_c v_c^T = sum_c sign_c (sqrt|w_c| v_c)(sqrt|w_c| v_c)^T
     if ((rc = eig_gather(st, ws.V, (int)n, ws.iwork, (int)n, ws.w, 1, ws.Cf, ws.sign))) return rc;

@@ -123,6 +123,21 @@ def test_c2_fp64_full(pkg, c2):
     assert np.array_equal(K, K.T)
     ej, ej_o = 0.5 * float(rho @ rho), 0.5 * float(rho_o @ rho_o)
     assert abs(ej - ej_o) < 1e-10 * abs(ej_o)
+    # K from the density itself (two factors (D, I) at this size): the whole K
+    # against the same oracle K, and an indefinite density on sampled rows
+    h = pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao)
+    K_d = host(h.K(D=torch.from_numpy(D).cuda()))
+    err_kd = max_rel(K_d, K_o)
+    assert err_kd < 1e-10 and np.array_equal(K_d, K_d.T), err_kd
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((cfg.nao, cfg.nao))
+    A = A + A.T
+    K_a = host(h.K(D=torch.from_numpy(A).cuda()))
+    h.close()
+    rows = sample_rows(cfg.nao)
+    K_a_o = oracle.K_pair_rows(row_slices(cfg, R, rows), A, np.eye(cfg.nao))
+    err_ka = float(np.abs(K_a[np.ix_(rows, rows)] - K_a_o).max() / np.abs(K_a_o).max())
+    assert err_ka < 1e-10, err_ka
     # DF diagonal from the same J stream
     h = pkg.Handle(torch.from_numpy(B).cuda(), cfg.nao)
     Jd = torch.empty((cfg.nao, cfg.nao), dtype=torch.float64, device="cuda")
@@ -143,6 +158,7 @@ def test_c2_fp64_full(pkg, c2):
     Jm = host(Jm)
     assert max_rel(Jm[0], J_o) < 1e-10
     assert max_rel(Jm[1], oracle.J(B, cfg.nao, Ds[1])) < 1e-10
+    print(f"C2 FP64: K from D {err_kd:.1e}, indefinite D rows {err_ka:.1e}")
     print(f"C2 FP64: rho {max_rel(rho, rho_o):.1e} J {max_rel(J, J_o):.1e} K {err_k:.1e} "
           f"E_J {ej_o:.10f} Eh, diff {ej - ej_o:.1e}; DF diagonal {err_d:.1e}")
 

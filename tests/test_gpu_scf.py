@@ -1,8 +1,9 @@
 """Density path of K and the GPU SCF step against the FP64 oracle.
 
-* K from a general symmetric D (signed eigen-factors on the GPU) equals the
-  oracle's sum_P B_P D B_P (1e-10 relative), also for D = 2CC^T (then equal
-  to K from C) and for an indefinite D.
+* K from a general symmetric D (signed eigen-factors on the GPU below
+  nao=256, the two factors (D, I) from there on) equals the oracle's
+  sum_P B_P D B_P (1e-10 relative), also for D = 2CC^T (then equal to K
+  from C) and for an indefinite D.
 * SCF: energies and error norms of iterations 1..10 match the oracle SCF
   (same algorithm) within 1e-10 relative; the converged energy matches; the
   converged density is idempotent with trace 2 nocc.  With B = 0 the first
@@ -26,7 +27,7 @@ def pkg():
     return p
 
 
-@pytest.mark.parametrize("nao,naux,seed", [(64, 50, 41), (131, 20, 42)])
+@pytest.mark.parametrize("nao,naux,seed", [(64, 50, 41), (131, 20, 42), (300, 30, 43)])
 def test_K_from_density(pkg, nao, naux, seed):
     print(f"case nao={nao} naux={naux} seed={seed}", flush=True)
     R, B, C = system(nao, naux, nao // 5, seed)
