@@ -199,10 +199,11 @@ int dfjk_build_J_diag(dfjk_handle h, const double* D_dev, double* J_dev, double*
  *                     (nao x nocc, 1 <= nocc <= nao), i.e. K for D = 2 C C^T.
  *   Cocc_dev == NULL: K = sum_P B_P D B_P for the symmetric D_dev (paper
  *                     Sec. IV.A.1: a guess density need not be idempotent),
- *                     through the signed eigen-factors of D for nao < 256,
- *                     and for nao >= 256 as the two-factor form of
- *                     dfjk_build_K_pair with L = D, R = I, sym = 1, scale
- *                     1/2 (workspace: X for 2 * naux * nao rows).
+ *                     through the signed eigen-factors of D for nao < 256
+ *                     or a reserved workspace (max_ncol > 0), else as the
+ *                     two-factor form of dfjk_build_K_pair with L = D,
+ *                     R = I, sym = 1, scale 1/2 (workspace: X for
+ *                     2 * naux * nao rows).
  * Deterministic.
  */
 int dfjk_build_K(dfjk_handle h, const double* Cocc_dev, int64_t nocc, const double* D_dev,

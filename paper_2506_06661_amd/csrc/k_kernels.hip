@@ -151,9 +151,10 @@ __device__ inline void g1_addr_next(G1Addr<NI, WM>& ad, int64_t nu0, int64_t ldc
 // reads and spreads the transposed writes over all banks.  FP64 reads go 16
 // lanes at a time, so the FP64 tiles keep a pitch of one extra element.  The
 // per-row XOR costs address registers: on MI355X the bank-free layout was
-// faster only for FP32 storage and the (5, 1) tile (the FP32 default: 26.0 ->
-// 25.0 ms at nao=1024, naux=4096, nocc=200); wider tiles and 16-bit storage
-// lost occupancy and ran up to 1.6x slower, so they keep the padded layout.
+// faster only for FP32 storage and the (5, 1) tile (26.0 -> 25.0 ms at
+// nao=1024, naux=4096, nocc=200); for the (13, 1) tile it ran 22.1 against
+// 21.6 ms (FP32 B) and 460 against 450 ms (BF16 B, nao=2048, nocc=400), so
+// the other tiles keep the padded layout.
 template <typename T, typename TS, int NI, int WM>
 constexpr bool g1_bankfree() { return sizeof(T) == 4 && sizeof(TS) == 4 && WM == 1 && NI <= 5; }
 template <typename T, typename TS, int NI, int WM>

@@ -297,10 +297,11 @@ int k_build_from_D(dfjk_ctx* h, const double* D, double* K) {
     const hipStream_t st = h->stream;
     symmetrize_kernel<<<dim3((unsigned)cdiv(n * n, 256)), 256, 0, st>>>(D, n, ws.A);
     DFJK_LAUNCH_CHECK("symmetrize_kernel");
-    if (n >= kPairFromD) {
+    if (n >= kPairFromD && h->opts.max_ncol == 0) {
         // K = 1/2 sum_P [(B_P D)(B_P I)^T + (B_P I)(B_P D)^T]: two factors of
         // nao columns each, no eigensolver (whose one-workgroup sweeps take
-        // seconds from nao ~ 500 on)
+        // seconds from nao ~ 500 on); a reserved workspace (at most nao
+        // columns) keeps the eigen-factor path, which fits it
         identity_kernel<<<dim3((unsigned)cdiv(n * n, 256)), 256, 0, st>>>(n, ws.V);
         DFJK_LAUNCH_CHECK("identity_kernel");
         return k_build_pair(h, ws.A, ws.V, n, 1, 0.5, K);
