@@ -22,7 +22,7 @@ def pkg():
 
 
 @pytest.mark.parametrize("naux,ncol,pad,seed", [(1, 5, 0, 1), (64, 64, 0, 2), (100, 257, 3, 3),
-                                                (300, 1000, 0, 4), (129, 77, 5, 5)])
+                                                (300, 1000, 0, 4), (129, 77, 5, 5), (300, 300, 1, 6)])
 def test_form_B(pkg, naux, ncol, pad, seed):
     print(f"form_B naux={naux} ncol={ncol} pad={pad}", flush=True)
     M = synth.metric(seed, naux)
