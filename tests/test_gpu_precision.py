@@ -97,7 +97,8 @@ def test_reduced_J_K(pkg, dtype, nao, naux, nocc, seed, ld_pad):
 
 
 @pytest.mark.parametrize("dtype,bound", [(BF16, 2 * 2.0 ** -8 + 5e-4), (F16, 2 * 2.0 ** -11 + 5e-4)])
-@pytest.mark.parametrize("nao,naux,nocc,seed", [(64, 256, 16, 1), (300, 40, 37, 33), (129, 20, 40, 34)])
+@pytest.mark.parametrize("nao,naux,nocc,seed", [(64, 256, 16, 1), (300, 40, 37, 33), (129, 20, 40, 34),
+                                              (1, 3, 1, 35), (65, 7, 65, 36)])
 def test_k16_exchange(pkg, dtype, bound, nao, naux, nocc, seed):
     """K on the 16-bit matrix cores (dense 16-bit copy of B).  Reference: the
     oracle on the dequantised B with C rounded once to the same format.  X is
