@@ -67,7 +67,13 @@ enum {
     DFJK_W_NOT_CONVERGED = 1
 };
 
-/* Options; pass NULL to dfjk_init for the defaults shown. */
+/*
+ * Options; pass NULL to dfjk_init for the defaults shown.  There is no
+ * determinism switch: every build sums its split partials in a fixed order,
+ * so J and K are bitwise reproducible for a given tile choice.  Tile choices
+ * are made per handle with dfjk_set_tile and, for batches, by
+ * dfjk_batch_autotune, whose cache_path argument is the tuning cache.
+ */
 typedef struct {
     int diis_space;       /* Pulay DIIS history length (8) */
     double conv_tol;      /* |E_k - E_{k-1}| threshold (1e-9) */
@@ -76,14 +82,16 @@ typedef struct {
     int compensated_j;    /* reduced-precision B, J accumulation: 2 = FP64 (default),
                              1 = compensated FP32 (Dot2), 0 = plain FP32 */
     int k16;              /* BF16/FP16 B, exchange from C: 1 = 16-bit matrix cores
-                             (the handle keeps a dense 16-bit copy of B, naux *
-                             ceil64(nao) * (ceil64(nao) + 64) elements, made in
-                             dfjk_init when
-                             max_ncol > 0, else on the first K call; K then
-                             uses B's contents as they were when the copy was
-                             made: call dfjk_update_B after changing them; C
-                             and X rounded to the 16-bit format); 0 = B
-                             dequantised on load, FP32 matrix cores (default) */
+                             (with the default GEMM1 tile the handle keeps a
+                             dense 16-bit copy of B, naux * ceil64(nao) *
+                             (ceil64(nao) + 64) elements, made in dfjk_init
+                             when max_ncol > 0, else on the first K call; K
+                             then uses B's contents as they were when the copy
+                             was made: call dfjk_update_B after changing them;
+                             the packed-triangle GEMM1 tiles, DFJK_TILE_K16
+                             8..12, read B itself and use no copy; C and X
+                             rounded to the 16-bit format); 0 = B dequantised
+                             on load, FP32 matrix cores (default) */
     int max_ncol;         /* 0 (default): workspace grows on demand, so a call
                              may allocate.  1..nao: dfjk_init reserves every
                              workspace buffer for K with up to max_ncol columns
