@@ -356,3 +356,55 @@ def test_c3_16bit_full(pkg, c3, dtype):
         "slice_E_K16_err_i_Eh": ek(Ks16) - ek(Ks_i), "slice_E_K16_err_ii_Eh": ek(Ks16) - ek(Ks16_ii)}
     print(f"C3 dtype {dtype}: " + ", ".join(f"{k} {v:.3e}" for k, v in report.items()))
     assert math.isfinite(ej)
+
+
+# ---------------------------------------------------------------- C4 size
+def test_c4_full_batch_sampled(pkg):
+    """The 256-molecule batch as the batch bench builds it (nao ~ U{40..400},
+    naux = 4 nao, nocc = nao // 5, BF16 B, graph-captured), with the FP32
+    exchange and with the 16-bit one: J and K of sampled molecules (the two
+    largest, the two smallest, two in between) against the oracle on the
+    stored B, at the bounds of the small batch tests (FP32 exchange 2e-4;
+    16-bit exchange 2u + 5e-4 with C rounded to BF16)."""
+    sizes = synth.batch_sizes()
+    order = np.argsort(sizes, kind="stable")
+    picks = sorted(set([int(order[-1]), int(order[-2]), int(order[0]), int(order[1]),
+                        int(order[len(order) // 3]), int(order[2 * len(order) // 3])]))
+    print(f"c4 batch: {len(sizes)} molecules, checking {[int(sizes[i]) for i in picks]}", flush=True)
+    mols = []
+    for i, nao in enumerate(sizes):
+        nao = int(nao)
+        seed = 4000 + i
+        R = synth.cluster_positions(seed, nao)
+        B = torch.from_numpy(synth.B_full(seed, R, 4 * nao)).cuda()
+        C = synth.C_occ(seed, nao, max(nao // 5, 1))
+        Cd = torch.from_numpy(C).cuda()
+        Bq = torch.empty(B.shape, dtype=torch.bfloat16, device="cuda")
+        pkg.dfjk_quantize(B, Bq, BF16, B.numel())
+        del B
+        mols.append({"B": Bq, "nao": nao, "D": 2.0 * Cd @ Cd.T, "C": Cd,
+                     "J": torch.empty((nao, nao), dtype=torch.float64, device="cuda"),
+                     "K": torch.empty((nao, nao), dtype=torch.float64, device="cuda")})
+    torch.cuda.synchronize()
+    bt = pkg.Batch(mols, BF16)
+    refs = {}
+    for i in picks:
+        nao = int(sizes[i])
+        R = synth.cluster_positions(4000 + i, nao)
+        Bq = oracle.quantize_bf16(synth.B_full(4000 + i, R, 4 * nao))
+        C = host(mols[i]["C"])
+        refs[i] = (oracle.J(Bq, nao, 2.0 * C @ C.T), oracle.K_C(Bq, nao, C),
+                   oracle.K_C(Bq, nao, oracle.quantize_bf16(C)))
+    for k16 in (False, True):
+        bt.set_k16(k16)
+        bt.capture()
+        bt.launch()
+        torch.cuda.synchronize()
+        for i in picks:
+            J_o, K_o, K_o16 = refs[i]
+            ej = max_rel(host(mols[i]["J"]), J_o)
+            ek = max_rel(host(mols[i]["K"]), K_o16 if k16 else K_o)
+            print(f"  k16={k16} nao={int(sizes[i])}: J {ej:.1e} K {ek:.1e}", flush=True)
+            assert ej < 1e-10
+            assert ek < (2 * 2.0 ** -8 + 5e-4 if k16 else 2e-4)
+    bt.close()
