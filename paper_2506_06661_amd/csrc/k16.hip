@@ -531,6 +531,11 @@ __global__ __launch_bounds__(kT, 1) void syrk_16w(const H* __restrict__ X, int64
             for (int ti = 0; ti < 8; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < 8; ++tj) acc[ti][tj] = Mma16<H>::step(a[ti], b[tj], acc[ti][tj]);
+            // all 16 operand reads before the first product: left to itself
+            // the compiler re-read 7 of the fragments into one register set,
+            // each read waited for before its 8 products
+            __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 64, 0);
             if (more) store(buf ^ 1);
             __syncthreads();
         }
@@ -934,7 +939,7 @@ __device__ __attribute__((always_inline)) inline void g1p_body(int64_t lid, cons
                 // wide tiles: several operand reads in flight ahead of the
                 // products: R0 reads, then (FM products, 1 read) until the
                 // reads run out (narrow tiles keep the compiler's order, which
-                // needs half the registers)
+                // measured the same)
                 constexpr int NR = FM + FN, R0 = 6 < NR ? 6 : NR;
                 __builtin_amdgcn_sched_group_barrier(0x100, R0, 0);
 #pragma unroll
