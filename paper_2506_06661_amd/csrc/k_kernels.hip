@@ -410,7 +410,10 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
     constexpr int PS = sizeof(T) == 4 ? SY_T + 16 : SY_T + 1;
     __shared__ T sA[2][KC][PS];
     __shared__ T sB[2][KC][PS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // the wave index is the same in all lanes: keep it (and what follows from
+    // it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int64_t t = lid % ntl;
     int64_t I, J;
@@ -428,6 +431,32 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
     const int64_t s = lid / ntl;
     const int64_t kbeg = s * kchunk;
     const int64_t kend = kbeg + kchunk < nrows ? kbeg + kchunk : nrows;
+
+    // Wave -> 64 x 64 sub-tile (rows ab.., columns bb.. of the tile) and the
+    // 16 x 16 blocks of it that are computed: those the finish reads (rows
+    // and columns below nao, on or below the diagonal of K).  Off the
+    // diagonal the four waves take the 2 x 2 sub-tiles; a diagonal tile of a
+    // symmetric result needs 36 of the 64 blocks, spread as the two halves
+    // of its lower-left sub-tile (8 blocks each) and the lower block
+    // triangles of the two diagonal sub-tiles (10 each).  The blocks computed
+    // come out bitwise as with the plain 2 x 2 split.
+    const bool diag = MODE != SY_PAIR_FULL && I == J;
+    int ab = wm * 64, bb = wn * 64;
+    uint32_t pat = 0xFFFFu;
+    if (diag) {
+        ab = wave == 2 ? 0 : 64;
+        bb = wave == 3 ? 64 : 0;
+        pat = wave == 0 ? 0x00FFu : wave == 1 ? 0xFF00u : 0xF731u;
+    }
+    uint32_t live = 0;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj) {
+            const bool on = mu0 + ab + ti * 16 < nao && nu0 + bb + tj * 16 < nao;
+            live |= (uint32_t)on << (ti * 4 + tj);
+        }
+    live &= pat;
 
     typename Mma<T>::acc_t acc[4][4];
 #pragma unroll
@@ -449,21 +478,22 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
             const int buf = ch & 1;
             const bool more = ch + 1 < nchunks;
             if (more)
-                sy_load<T, MODE>(st, X, ldx, nrows, nao, ncol, sign, kbeg + (ch + 1) * KC, kend, mu0, nu0, boff,
-                                 tid);
+                sy_load<T, MODE>(st, X, ldx, nrows, nao, ncol, sign, kbeg + (ch + 1) * KC, kend, mu0, nu0,
+                                 boff, tid);
 #pragma unroll
             for (int kk = 0; kk < KC / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
                 T a[4], b[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    a[q] = sA[buf][kr][wm * 64 + q * 16 + (lane & 15)];
-                    b[q] = sB[buf][kr][wn * 64 + q * 16 + (lane & 15)];
+                    a[q] = sA[buf][kr][ab + q * 16 + (lane & 15)];
+                    b[q] = sB[buf][kr][bb + q * 16 + (lane & 15)];
                 }
 #pragma unroll
                 for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
+                    for (int tj = 0; tj < 4; ++tj)
+                        if ((live >> (ti * 4 + tj)) & 1u) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
             }
             if (more) {
 #pragma unroll
@@ -479,13 +509,15 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj)
+        for (int tj = 0; tj < 4; ++tj) {
+            if (!((live >> (ti * 4 + tj)) & 1u)) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int m = wm * 64 + ti * 16 + Mma<T>::row(lane, r);
-                const int n = wn * 64 + tj * 16 + (lane & 15);
+                const int m = ab + ti * 16 + Mma<T>::row(lane, r);
+                const int n = bb + tj * 16 + (lane & 15);
                 out[m * SY_T + n] = acc[ti][tj][r];
             }
+        }
 }
 
 template <typename T, int MODE = SY_SYM>
