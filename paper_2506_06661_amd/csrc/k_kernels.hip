@@ -364,8 +364,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, in
 }
 
 // ---------------------------------------------------------------- GEMM2 (SYRK)
+// Staging of one KC-deep chunk of the two 128-wide operand panels, 8
+// elements of each per thread.  Vector form (rows 16-byte aligned): each
+// load moves V = 16 / sizeof(T) consecutive elements of a row, rows RPP
+// apart.  Element form (any row stride): one element per load, the 256
+// threads covering two rows of 128 per pass.
 template <typename T>
 struct SyStage {
+    static constexpr int V = 16 / sizeof(T);          // elements per vector load
+    static constexpr int TPR = SY_T / V;              // threads per panel row
+    static constexpr int RPP = kThreads / TPR;        // rows per pass
+    static constexpr int NP = KC / RPP;               // passes per chunk
     T a[8], b[8];
 };
 
@@ -377,32 +386,90 @@ struct SyStage {
 // transpose (sum_k xL_k xR_k^T + xR_k xL_k^T, a symmetric result).
 enum { SY_SYM = 0, SY_PAIR_LOWER = 1, SY_PAIR_FULL = 2 };
 
-template <typename T, int MODE>
-__device__ inline void sy_load(SyStage<T>& st, const T* __restrict__ X, int64_t ldx, int64_t nrows,
-                               int64_t nao, int64_t ncol, const double* __restrict__ sign, int64_t k0,
-                               int64_t kend, int64_t mu0, int64_t nu0, int64_t boff, int tid) {
+// V elements of row xr from column c0 (zeros at or past nao); one 16-byte
+// load when all of them are below nao
+template <typename T>
+__device__ inline void sy_vec(T* v, const T* __restrict__ xr, int64_t c0, int64_t nao, bool ok) {
+    constexpr int V = SyStage<T>::V;
+    if (ok && c0 + V <= nao) {
+        __builtin_memcpy(v, xr + c0, 16);
+    } else {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = tid / SY_T + 2 * j, m = tid % SY_T;
+        for (int e = 0; e < V; ++e) v[e] = (ok && c0 + e < nao) ? xr[c0 + e] : T(0);
+    }
+}
+
+template <typename T, int MODE, bool VEC>
+__device__ inline void sy_load(SyStage<T>& st, const T* __restrict__ X, int64_t ldx,
+                               int64_t nrows, int64_t nao, int64_t ncol, const double* __restrict__ sign,
+                               int64_t k0, int64_t kend, int64_t mu0, int64_t nu0, int64_t boff, int tid) {
+    using S = SyStage<T>;
+    auto rows = [&](int k, const T*& xr, const T*& xb, bool& ok, bool& neg) {
         const int64_t row = k0 + k;
-        const bool ok = row < kend;
-        const T* xr = X + row * ldx;
-        const T* xb = xr;
+        ok = row < kend;
+        xr = X + row * ldx;
+        xb = xr;
         if constexpr (MODE != SY_SYM) {
             const int64_t rb = row + boff;
             xb = X + (rb >= 2 * boff ? rb - 2 * boff : rb) * ldx;
         }
-        st.a[j] = (ok && mu0 + m < nao) ? xr[mu0 + m] : T(0);
-        T bv = (ok && nu0 + m < nao) ? xb[nu0 + m] : T(0);
-        if (sign && ok && sign[row % ncol] < 0) bv = -bv;
-        st.b[j] = bv;
+        neg = sign && ok && sign[row % ncol] < 0;
+    };
+    if constexpr (VEC) {
+#pragma unroll
+        for (int p = 0; p < S::NP; ++p) {
+            const int k = tid / S::TPR + S::RPP * p, m = (tid % S::TPR) * S::V;
+            const T *xr, *xb;
+            bool ok, neg;
+            rows(k, xr, xb, ok, neg);
+            sy_vec<T>(&st.a[p * S::V], xr, mu0 + m, nao, ok);
+            sy_vec<T>(&st.b[p * S::V], xb, nu0 + m, nao, ok);
+#pragma unroll
+            for (int e = 0; e < S::V; ++e)
+                if (neg) st.b[p * S::V + e] = -st.b[p * S::V + e];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = tid / SY_T + 2 * j, m = tid % SY_T;
+            const T *xr, *xb;
+            bool ok, neg;
+            rows(k, xr, xb, ok, neg);
+            st.a[j] = (ok && mu0 + m < nao) ? xr[mu0 + m] : T(0);
+            const T bv = (ok && nu0 + m < nao) ? xb[nu0 + m] : T(0);
+            st.b[j] = neg ? -bv : bv;
+        }
+    }
+}
+
+template <typename T, bool VEC>
+__device__ inline void sy_store(const SyStage<T>& st, T (*sA)[SY_T + (sizeof(T) == 4 ? 16 : 1)],
+                                T (*sB)[SY_T + (sizeof(T) == 4 ? 16 : 1)], int tid) {
+    using S = SyStage<T>;
+    if constexpr (VEC) {
+#pragma unroll
+        for (int p = 0; p < S::NP; ++p) {
+            const int k = tid / S::TPR + S::RPP * p, m = (tid % S::TPR) * S::V;
+#pragma unroll
+            for (int e = 0; e < S::V; ++e) {
+                sA[k][m + e] = st.a[p * S::V + e];
+                sB[k][m + e] = st.b[p * S::V + e];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sA[tid / SY_T + 2 * j][tid % SY_T] = st.a[j];
+            sB[tid / SY_T + 2 * j][tid % SY_T] = st.b[j];
+        }
     }
 }
 
 // partial[(s*ntl + t)][m][n] = sum_{k in split s} X[k][mu0+m] * sign_k * X[k'][nu0+n]
 // (k' = k, or the row paired with k for two factors); block id = s*ntl + t,
-// t a lower tile (I >= J) or, for SY_PAIR_FULL, any tile (I = t / nt)
-template <typename T, int MODE = SY_SYM>
+// t a lower tile (I >= J) or, for SY_PAIR_FULL, any tile (I = t / nt).
+// VEC: staging with 16-byte loads (X and ldx * sizeof(T) 16-byte aligned).
+template <typename T, int MODE = SY_SYM, bool VEC = false>
 __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                    int64_t nao, int64_t ncol, const double* __restrict__ sign,
                                    int64_t kchunk, int64_t ntl, T* __restrict__ part, int64_t boff = 0) {
@@ -467,19 +534,15 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
     if (kbeg < kend) {
         const int64_t nchunks = cdiv(kend - kbeg, KC);
         SyStage<T> st;
-        sy_load<T, MODE>(st, X, ldx, nrows, nao, ncol, sign, kbeg, kend, mu0, nu0, boff, tid);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            sA[0][tid / SY_T + 2 * j][tid % SY_T] = st.a[j];
-            sB[0][tid / SY_T + 2 * j][tid % SY_T] = st.b[j];
-        }
+        sy_load<T, MODE, VEC>(st, X, ldx, nrows, nao, ncol, sign, kbeg, kend, mu0, nu0, boff, tid);
+        sy_store<T, VEC>(st, sA[0], sB[0], tid);
         __syncthreads();
         for (int64_t ch = 0; ch < nchunks; ++ch) {
             const int buf = ch & 1;
             const bool more = ch + 1 < nchunks;
             if (more)
-                sy_load<T, MODE>(st, X, ldx, nrows, nao, ncol, sign, kbeg + (ch + 1) * KC, kend, mu0, nu0,
-                                 boff, tid);
+                sy_load<T, MODE, VEC>(st, X, ldx, nrows, nao, ncol, sign, kbeg + (ch + 1) * KC, kend, mu0,
+                                      nu0, boff, tid);
 #pragma unroll
             for (int kk = 0; kk < KC / 4; ++kk) {
                 const int kr = kk * 4 + (lane >> 4);
@@ -495,13 +558,7 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
                     for (int tj = 0; tj < 4; ++tj)
                         if ((live >> (ti * 4 + tj)) & 1u) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
             }
-            if (more) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    sA[buf ^ 1][tid / SY_T + 2 * j][tid % SY_T] = st.a[j];
-                    sB[buf ^ 1][tid / SY_T + 2 * j][tid % SY_T] = st.b[j];
-                }
-            }
+            if (more) sy_store<T, VEC>(st, sA[buf ^ 1], sB[buf ^ 1], tid);
             __syncthreads();
         }
     }
@@ -520,14 +577,14 @@ __device__ __attribute__((always_inline)) inline void k_syrk_body(int64_t lid, c
         }
 }
 
-template <typename T, int MODE = SY_SYM>
+template <typename T, int MODE = SY_SYM, bool VEC = false>
 __global__ __launch_bounds__(kThreads) void k_syrk(const T* __restrict__ X, int64_t ldx, int64_t nrows,
                                                     int64_t nao, int64_t ncol,
                                                     const double* __restrict__ sign, int64_t kchunk,
                                                     int64_t ntl, int64_t nblk, T* __restrict__ part,
                                                     int64_t boff) {
     // all tiles of one split run on one XCD and share its L2 copy of the X rows
-    k_syrk_body<T, MODE>(xcd_logical(blockIdx.x, nblk), X, ldx, nrows, nao, ncol, sign, kchunk, ntl, part,
+    k_syrk_body<T, MODE, VEC>(xcd_logical(blockIdx.x, nblk), X, ldx, nrows, nao, ncol, sign, kchunk, ntl, part,
                          boff);
 }
 
@@ -775,8 +832,12 @@ int k_build_t(dfjk_ctx* h, const void* C, int64_t ncol, const double* sign, doub
     syrk_splits(nrows, ntl, sizeof(T) == 4, &nsplit, &kchunk);
     T* part = static_cast<T*>(h->kpart.ptr);
     h->prof.begin(PH_K_SYRK, h->stream);
-    k_syrk<T><<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
-        X, ldx, nrows, h->nao, ncol, sign, kchunk, ntl, ntl * nsplit, part, 0);
+    if (ldx % SyStage<T>::V == 0)
+        k_syrk<T, SY_SYM, true><<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
+            X, ldx, nrows, h->nao, ncol, sign, kchunk, ntl, ntl * nsplit, part, 0);
+    else
+        k_syrk<T><<<dim3((unsigned)(ntl * nsplit)), kThreads, 0, h->stream>>>(
+            X, ldx, nrows, h->nao, ncol, sign, kchunk, ntl, ntl * nsplit, part, 0);
     h->prof.end(PH_K_SYRK, h->stream);
     DFJK_LAUNCH_CHECK("k_syrk");
     h->prof.begin(PH_K_FINISH, h->stream);
@@ -816,9 +877,16 @@ int k_build_pair_t(dfjk_ctx* h, const void* L, const void* R, int64_t ncol, int 
     T* part = static_cast<T*>(h->kpart.ptr);
     const dim3 grid((unsigned)(ntl * nsplit));
     h->prof.begin(PH_K_SYRK, h->stream);
-    if (sym)
+    const bool vec = ldx % SyStage<T>::V == 0;
+    if (sym && vec)
+        k_syrk<T, SY_PAIR_LOWER, true><<<grid, kThreads, 0, h->stream>>>(X, ldx, nrows, h->nao, ncol, nullptr,
+                                                                           kchunk, ntl, ntl * nsplit, part, n1);
+    else if (sym)
         k_syrk<T, SY_PAIR_LOWER><<<grid, kThreads, 0, h->stream>>>(X, ldx, nrows, h->nao, ncol, nullptr, kchunk,
                                                                      ntl, ntl * nsplit, part, n1);
+    else if (vec)
+        k_syrk<T, SY_PAIR_FULL, true><<<grid, kThreads, 0, h->stream>>>(X, ldx, nrows, h->nao, ncol, nullptr,
+                                                                          kchunk, ntl, ntl * nsplit, part, n1);
     else
         k_syrk<T, SY_PAIR_FULL><<<grid, kThreads, 0, h->stream>>>(X, ldx, nrows, h->nao, ncol, nullptr, kchunk,
                                                                     ntl, ntl * nsplit, part, n1);
