@@ -53,9 +53,13 @@ __device__ inline float to_compute<float, _Float16>(_Float16 x) {
 // ---------------------------------------------------------------- GEMM1
 // Workgroup tile: BI = 16*NI rows i (all waves) x BM = 64*WM columns mu
 // (each of the 4 waves owns 16*WM columns).  Per 16-deep nu chunk each thread
-// stages V = 16 / sizeof(T) consecutive orbitals of a row of C per load (a
-// 16-byte load when C's rows are 16-byte aligned and all V lie below ncol)
-// and 4*WM elements of B_P, in registers, then LDS.
+// stages its share of C (VC consecutive orbitals of a row per load) and of
+// B_P (VB consecutive elements of a packed row per load: along nu below the
+// diagonal, along mu above it) in registers, then LDS.  VC = VB = 1 is one
+// element per load; the wider forms use 16-byte loads of C where its rows
+// are 16-byte aligned and loads of up to 16 bytes of B at any alignment (the
+// GPU's global loads take unaligned addresses), with element loads at the
+// edges (past ncol or nao).
 //
 // Address arithmetic is incremental: a thread's C elements and its
 // below-diagonal B elements (packed row mu, column nu) advance by a constant
@@ -63,32 +67,49 @@ __device__ inline float to_compute<float, _Float16>(_Float16 x) {
 // the triangular row starts T(nu + 16) = T(nu) + 16 nu + 136.
 template <typename T, int NI, int VC>
 struct G1C {
-    static constexpr int V = VC;                  // orbitals per load (1, or 16 bytes' worth)
+    static constexpr int V = VC;                  // orbitals per load
     static constexpr int VPR = 16 * NI / V;       // loads per row of the C tile
     static constexpr int NV = KC * VPR;           // loads per chunk
     static constexpr int NCV = (NV + kThreads - 1) / kThreads;  // per thread
 };
 
-template <typename T, int NI, int WM, int VC>
+// B elements per load: with wide C staging, 16 bytes' worth, at most the
+// 4*WM elements a thread stages per chunk
+template <typename TS, int WM, int VC>
+constexpr int g1_vb() {
+    return VC == 1 ? 1 : (4 * WM < (int)(16 / sizeof(TS)) ? 4 * WM : (int)(16 / sizeof(TS)));
+}
+
+template <int WM, int VB>
+struct G1B {
+    static constexpr int NP = 4 * WM / VB;        // loads per thread per chunk
+    static constexpr int TLO = KC / VB;           // below: threads per packed row mu
+    static constexpr int RLO = kThreads / TLO;    // below: rows mu per pass
+    static constexpr int TUP = 64 * WM / VB;      // above: threads per packed row nu
+    static constexpr int RUP = kThreads / TUP;    // above: rows nu per pass
+};
+
+template <typename T, int NI, int WM, int VC, int VB>
 struct G1Stage {
-    T b[4 * WM];
+    T b[G1B<WM, VB>::NP][VB];
     T c[G1C<T, NI, VC>::NCV][VC];
 };
 
-template <typename T, int NI, int WM, int VC>
+template <typename T, int NI, int WM, int VC, int VB>
 struct G1Addr {
     int64_t c_off[G1C<T, NI, VC>::NCV];  // offset of C[nu0 + k][i] for the current chunk
     int c_lim[G1C<T, NI, VC>::NCV];      // orbitals below ncol among the VC (0 for no load)
-    int64_t lo_off[4 * WM];          // below-diagonal: mu(mu+1)/2 + nu0 + k
-    int64_t up_row[4 * WM];          // above-diagonal: T(nu0 + k)
-    bool mu_ok_lo[4 * WM], mu_ok_up;
+    int64_t lo_off[G1B<WM, VB>::NP];     // below-diagonal: mu(mu+1)/2 + nu0 + k
+    int64_t up_row[G1B<WM, VB>::NP];     // above-diagonal: T(nu0 + k)
+    bool mu_ok_lo[G1B<WM, VB>::NP];
+    int up_lim;                          // above: columns mu below nao among the VB
 };
 
-template <typename T, int NI, int WM, int VC>
-__device__ inline void g1_addr_init(G1Addr<T, NI, WM, VC>& ad, int64_t nao, int64_t ldc, int64_t ncol,
+template <typename T, int NI, int WM, int VC, int VB>
+__device__ inline void g1_addr_init(G1Addr<T, NI, WM, VC, VB>& ad, int64_t nao, int64_t ldc, int64_t ncol,
                                     int64_t mu0, int64_t i0, int tid) {
     using G = G1C<T, NI, VC>;
-    constexpr int BM = 64 * WM, ROWS = kThreads / BM;
+    using GB = G1B<WM, VB>;
 #pragma unroll
     for (int j = 0; j < G::NCV; ++j) {
         const int e = tid + j * kThreads;
@@ -98,22 +119,38 @@ __device__ inline void g1_addr_init(G1Addr<T, NI, WM, VC>& ad, int64_t nao, int6
         ad.c_lim[j] = e < G::NV ? (int)(lim < 0 ? 0 : lim > G::V ? G::V : lim) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < 4 * WM; ++j) {
-        const int64_t mu = mu0 + tid / KC + 16 * j;
-        ad.lo_off[j] = mu * (mu + 1) / 2 + tid % KC;
+    for (int j = 0; j < GB::NP; ++j) {
+        const int64_t mu = mu0 + tid / GB::TLO + GB::RLO * j;
+        ad.lo_off[j] = mu * (mu + 1) / 2 + (tid % GB::TLO) * VB;
         ad.mu_ok_lo[j] = mu < nao;
-        const int64_t nu = tid / BM + ROWS * j;
+        const int64_t nu = tid / GB::TUP + GB::RUP * j;
         ad.up_row[j] = nu * (nu + 1) / 2;
     }
-    ad.mu_ok_up = mu0 + tid % BM < nao;
+    const int64_t ul = nao - (mu0 + (tid % GB::TUP) * VB);
+    ad.up_lim = (int)(ul < 0 ? 0 : ul > VB ? VB : ul);
 }
 
-template <typename T, typename TS, int NI, int WM, int VC>
-__device__ inline void g1_load(G1Stage<T, NI, WM, VC>& st, const G1Addr<T, NI, WM, VC>& ad,
+// n consecutive elements of B (n = VB, or fewer: zeros after them), converted
+template <typename T, typename TS, int VB>
+__device__ inline void g1_bvec(T (&v)[VB], const TS* __restrict__ src, int n) {
+    if (VB > 1 && n == VB) {
+        TS w[VB];
+        __builtin_memcpy(w, src, VB * sizeof(TS));
+#pragma unroll
+        for (int e = 0; e < VB; ++e) v[e] = to_compute<T, TS>(w[e]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VB; ++e) v[e] = e < n ? to_compute<T, TS>(src[e]) : T(0);
+    }
+}
+
+template <typename T, typename TS, int NI, int WM, int VC, int VB>
+__device__ inline void g1_load(G1Stage<T, NI, WM, VC, VB>& st, const G1Addr<T, NI, WM, VC, VB>& ad,
                                const TS* __restrict__ Bp, int64_t nao,
                                const T* __restrict__ C, bool cvec, int64_t nu0, int64_t mu0, int tid) {
     using G = G1C<T, NI, VC>;
-    constexpr int BM = 64 * WM, ROWS = kThreads / BM;
+    using GB = G1B<WM, VB>;
+    constexpr int BM = 64 * WM;
 #pragma unroll
     for (int j = 0; j < G::NCV; ++j) {
         const int k = (tid + j * kThreads) / G::VPR;
@@ -128,36 +165,40 @@ __device__ inline void g1_load(G1Stage<T, NI, WM, VC>& st, const G1Addr<T, NI, W
     if (nu0 + KC <= mu0) {
         // every nu < mu: packed row mu, columns nu0 .. nu0+15
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) st.b[j] = ad.mu_ok_lo[j] ? to_compute<T, TS>(Bp[ad.lo_off[j]]) : T(0);
+        for (int j = 0; j < GB::NP; ++j) g1_bvec<T, TS, VB>(st.b[j], Bp + ad.lo_off[j], ad.mu_ok_lo[j] ? VB : 0);
     } else if (nu0 >= mu0 + BM - 1) {
         // every nu >= mu: packed row nu, columns mu0 .. mu0+BM-1
-        const int m = tid % BM;
+        const int m = (tid % GB::TUP) * VB;
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) {
-            const int64_t nu = nu0 + tid / BM + ROWS * j;
-            st.b[j] = (nu < nao && ad.mu_ok_up) ? to_compute<T, TS>(Bp[ad.up_row[j] + mu0 + m]) : T(0);
+        for (int j = 0; j < GB::NP; ++j) {
+            const int64_t nu = nu0 + tid / GB::TUP + GB::RUP * j;
+            g1_bvec<T, TS, VB>(st.b[j], Bp + ad.up_row[j] + mu0 + m, nu < nao ? ad.up_lim : 0);
         }
     } else {
-        // chunk crossing the diagonal
+        // chunk crossing the diagonal (above-diagonal layout, element loads)
+        const int m = (tid % GB::TUP) * VB;
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) {
-            const int k = tid / BM + ROWS * j, m = tid % BM;
-            const int64_t nu = nu0 + k, mu = mu0 + m;
-            st.b[j] = (nu < nao && mu < nao) ? to_compute<T, TS>(Bp[pidx(nu, mu)]) : T(0);
+        for (int j = 0; j < GB::NP; ++j) {
+            const int64_t nu = nu0 + tid / GB::TUP + GB::RUP * j;
+#pragma unroll
+            for (int e = 0; e < VB; ++e) {
+                const int64_t mu = mu0 + m + e;
+                st.b[j][e] = (nu < nao && mu < nao) ? to_compute<T, TS>(Bp[pidx(nu, mu)]) : T(0);
+            }
         }
     }
 }
 
 // Move the addresses from chunk nu0 to chunk nu0 + KC.
-template <typename T, int NI, int WM, int VC>
-__device__ inline void g1_addr_next(G1Addr<T, NI, WM, VC>& ad, int64_t nu0, int64_t ldc, int tid) {
-    constexpr int BM = 64 * WM, ROWS = kThreads / BM;
+template <typename T, int NI, int WM, int VC, int VB>
+__device__ inline void g1_addr_next(G1Addr<T, NI, WM, VC, VB>& ad, int64_t nu0, int64_t ldc, int tid) {
+    using GB = G1B<WM, VB>;
 #pragma unroll
     for (int j = 0; j < G1C<T, NI, VC>::NCV; ++j) ad.c_off[j] += (int64_t)KC * ldc;
 #pragma unroll
-    for (int j = 0; j < 4 * WM; ++j) {
+    for (int j = 0; j < GB::NP; ++j) {
         ad.lo_off[j] += KC;
-        const int64_t nu = nu0 + tid / BM + ROWS * j;
+        const int64_t nu = nu0 + tid / GB::TUP + GB::RUP * j;
         ad.up_row[j] += (int64_t)KC * nu + (KC * (KC + 1)) / 2;
     }
 }
@@ -185,11 +226,11 @@ constexpr int g1_pitch_b() { return g1_bankfree<T, TS, NI, WM>() ? 64 * WM + 16 
 template <typename T, typename TS, int NI, int WM>
 __device__ inline int g1_swz(int row) { return g1_bankfree<T, TS, NI, WM>() ? 2 * ((row >> 1) & 7) : 0; }
 
-template <typename T, typename TS, int NI, int WM, int VC>
-__device__ inline void g1_store(const G1Stage<T, NI, WM, VC>& st, T (*sC)[g1_pitch_c<T, TS, NI, WM>()],
+template <typename T, typename TS, int NI, int WM, int VC, int VB>
+__device__ inline void g1_store(const G1Stage<T, NI, WM, VC, VB>& st, T (*sC)[g1_pitch_c<T, TS, NI, WM>()],
                                 T (*sB)[g1_pitch_b<T, TS, NI, WM>()], bool lower, int tid) {
     using G = G1C<T, NI, VC>;
-    constexpr int BM = 64 * WM, ROWS = kThreads / BM;
+    using GB = G1B<WM, VB>;
 #pragma unroll
     for (int j = 0; j < G::NCV; ++j) {
         const int e = tid + j * kThreads;
@@ -200,14 +241,22 @@ __device__ inline void g1_store(const G1Stage<T, NI, WM, VC>& st, T (*sC)[g1_pit
         }
     }
     if (lower) {
-        const int r = tid % KC;
+        // element e of load j: row nu0 + (tid % TLO) * VB + e, column mu
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) sB[r][(tid / KC + 16 * j) ^ g1_swz<T, TS, NI, WM>(r)] = st.b[j];
+        for (int j = 0; j < GB::NP; ++j) {
+            const int m = tid / GB::TLO + GB::RLO * j;
+#pragma unroll
+            for (int e = 0; e < VB; ++e) {
+                const int r = (tid % GB::TLO) * VB + e;
+                sB[r][m ^ g1_swz<T, TS, NI, WM>(r)] = st.b[j][e];
+            }
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < 4 * WM; ++j) {
-            const int r = tid / BM + ROWS * j;
-            sB[r][(tid % BM) ^ g1_swz<T, TS, NI, WM>(r)] = st.b[j];
+        for (int j = 0; j < GB::NP; ++j) {
+            const int r = tid / GB::TUP + GB::RUP * j, m = (tid % GB::TUP) * VB;
+#pragma unroll
+            for (int e = 0; e < VB; ++e) sB[r][(m + e) ^ g1_swz<T, TS, NI, WM>(r)] = st.b[j][e];
         }
     }
 }
@@ -250,21 +299,22 @@ __device__ __attribute__((always_inline)) inline void k_gemm1_body(int64_t lid, 
         for (int b = 0; b < WM; ++b) acc[a][b] = Mma<T>::zero();
 
     const int64_t nchunks = cdiv(nao, KC);
-    G1Stage<T, NI, WM, VC> st;
-    G1Addr<T, NI, WM, VC> ad;
+    constexpr int VB = g1_vb<TS, WM, VC>();
+    G1Stage<T, NI, WM, VC, VB> st;
+    G1Addr<T, NI, WM, VC, VB> ad;
     // 16-byte loads of C where its rows are 16-byte aligned
     const bool cvec = VC > 1 && ldc % VC == 0 && i0 % VC == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
-    g1_addr_init<T, NI, WM, VC>(ad, nao, ldc, iend, mu0, i0, tid);
-    g1_load<T, TS, NI, WM, VC>(st, ad, Bp, nao, C, cvec, 0, mu0, tid);
-    g1_store<T, TS, NI, WM, VC>(st, sC[0], sB[0], KC <= mu0, tid);
+    g1_addr_init<T, NI, WM, VC, VB>(ad, nao, ldc, iend, mu0, i0, tid);
+    g1_load<T, TS, NI, WM, VC, VB>(st, ad, Bp, nao, C, cvec, 0, mu0, tid);
+    g1_store<T, TS, NI, WM, VC, VB>(st, sC[0], sB[0], KC <= mu0, tid);
     __syncthreads();
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
         const int64_t nnext = (ch + 1) * KC;
         const bool more = ch + 1 < nchunks;
         if (more) {
-            g1_addr_next<T, NI, WM, VC>(ad, ch * KC, ldc, tid);
-            g1_load<T, TS, NI, WM, VC>(st, ad, Bp, nao, C, cvec, nnext, mu0, tid);
+            g1_addr_next<T, NI, WM, VC, VB>(ad, ch * KC, ldc, tid);
+            g1_load<T, TS, NI, WM, VC, VB>(st, ad, Bp, nao, C, cvec, nnext, mu0, tid);
         }
 #pragma unroll
         for (int kk = 0; kk < KC / 4; ++kk) {
@@ -279,7 +329,7 @@ __device__ __attribute__((always_inline)) inline void k_gemm1_body(int64_t lid, 
 #pragma unroll
                 for (int tj = 0; tj < WM; ++tj) acc[ti][tj] = Mma<T>::step(a[ti], b[tj], acc[ti][tj]);
         }
-        if (more) g1_store<T, TS, NI, WM, VC>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
+        if (more) g1_store<T, TS, NI, WM, VC, VB>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
         __syncthreads();
     }
 #pragma unroll
@@ -328,21 +378,22 @@ __device__ __attribute__((always_inline)) inline void k_gemm1w_body(int64_t lid,
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
     const int64_t nchunks = cdiv(nao, KC);
-    G1Stage<float, NI, WM, VC> st;
-    G1Addr<float, NI, WM, VC> ad;
+    constexpr int VB = g1_vb<TS, WM, VC>();
+    G1Stage<float, NI, WM, VC, VB> st;
+    G1Addr<float, NI, WM, VC, VB> ad;
     // 16-byte loads of C where its rows are 16-byte aligned
     const bool cvec = VC > 1 && ldc % VC == 0 && i0 % VC == 0 && (reinterpret_cast<uintptr_t>(C) & 15) == 0;
-    g1_addr_init<float, NI, WM, VC>(ad, nao, ldc, iend, mu0, i0, tid);
-    g1_load<float, TS, NI, WM, VC>(st, ad, Bp, nao, C, cvec, 0, mu0, tid);
-    g1_store<float, TS, NI, WM, VC>(st, sC[0], sB[0], KC <= mu0, tid);
+    g1_addr_init<float, NI, WM, VC, VB>(ad, nao, ldc, iend, mu0, i0, tid);
+    g1_load<float, TS, NI, WM, VC, VB>(st, ad, Bp, nao, C, cvec, 0, mu0, tid);
+    g1_store<float, TS, NI, WM, VC, VB>(st, sC[0], sB[0], KC <= mu0, tid);
     __syncthreads();
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         const int buf = ch & 1;
         const int64_t nnext = (ch + 1) * KC;
         const bool more = ch + 1 < nchunks;
         if (more) {
-            g1_addr_next<float, NI, WM, VC>(ad, ch * KC, ldc, tid);
-            g1_load<float, TS, NI, WM, VC>(st, ad, Bp, nao, C, cvec, nnext, mu0, tid);
+            g1_addr_next<float, NI, WM, VC, VB>(ad, ch * KC, ldc, tid);
+            g1_load<float, TS, NI, WM, VC, VB>(st, ad, Bp, nao, C, cvec, nnext, mu0, tid);
         }
 #pragma unroll
         for (int kp = 0; kp < KC / 2; ++kp) {
@@ -359,7 +410,7 @@ __device__ __attribute__((always_inline)) inline void k_gemm1w_body(int64_t lid,
                 for (int tj = 0; tj < WJ; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
         }
-        if (more) g1_store<float, TS, NI, WM, VC>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
+        if (more) g1_store<float, TS, NI, WM, VC, VB>(st, sC[buf ^ 1], sB[buf ^ 1], nnext + KC <= mu0, tid);
         __syncthreads();
     }
 #pragma unroll
