@@ -384,8 +384,12 @@ int dfjk_batch_init(dfjk_batch* out, const dfjk_mol* mols, int nmol, int dtype, 
         offs.push_back(take(sizeof(double) * d.naux * d.j_chunks));
         offs.push_back(take(sizeof(double) * d.naux));
         offs.push_back(take(sizeof(double) * d.npair * d.j_splits));
-        offs.push_back(take(sizeof(float) * d.nao * d.nocc));
-        offs.push_back(take(sizeof(float) * nrows * d.nao));
+        // FP32 C and X rows padded to whole 16-byte vectors (the exchange
+        // kernels then stage them with 16-byte loads)
+        d.ldcf = cdiv(d.nocc, 4) * 4;
+        d.ldx = cdiv(d.nao, 4) * 4;
+        offs.push_back(take(sizeof(float) * d.nao * d.ldcf));
+        offs.push_back(take(sizeof(float) * nrows * d.ldx));
         offs.push_back(take(sizeof(float) * d.nsplit * d.ntl * 128 * 128));
         b->cost.push_back((double)d.naux * d.nao * d.nao * d.nocc);
     }

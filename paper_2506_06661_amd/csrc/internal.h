@@ -160,8 +160,9 @@ struct MolDesc {
     double* rho_part;  // naux x j_chunks
     double* rho;       // naux
     double* jpart;     // j_splits x npair
-    float* Cf;         // nao x nocc
-    float* X;          // naux*nocc x nao
+    float* Cf;         // nao x nocc, rows ldcf apart
+    float* X;          // naux*nocc x nao, rows ldx apart
+    int64_t ldcf, ldx; // nocc and nao rounded up to whole 16-byte vectors
     float* kpart;      // nsplit x ntl x 128 x 128
     int64_t j_chunks, j_splits, chunk, prows;
     int64_t nsplit, kchunk, ntl;

@@ -278,7 +278,7 @@ __device__ inline int64_t xcd_logical(int64_t hw, int64_t nblk) {
 // Columns [ioff, iend) of the ncol orbital columns (a launch may cover part of
 // them with one tile and the rest with another).
 // VC: orbitals of C per load (1, or 16 bytes' worth).
-template <typename T, typename TS, int NI, int WM, int VC = 1>
+template <typename T, typename TS, int NI, int WM, int VC = 1, int VB = g1_vb<TS, WM, VC>()>
 __device__ __attribute__((always_inline)) inline void k_gemm1_body(int64_t lid, const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                     const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                     T* __restrict__ X, int64_t ldx, int64_t nib, int64_t nmb,
@@ -299,7 +299,6 @@ __device__ __attribute__((always_inline)) inline void k_gemm1_body(int64_t lid, 
         for (int b = 0; b < WM; ++b) acc[a][b] = Mma<T>::zero();
 
     const int64_t nchunks = cdiv(nao, KC);
-    constexpr int VB = g1_vb<TS, WM, VC>();
     G1Stage<T, NI, WM, VC, VB> st;
     G1Addr<T, NI, WM, VC, VB> ad;
     // 16-byte loads of C where its rows are 16-byte aligned
@@ -1009,11 +1008,12 @@ __global__ __launch_bounds__(kThreads) void kb_kernel(int kind, const MolDesc* _
     switch (kind) {
         case BP_CF32: {
             const int64_t e = lid * kThreads + threadIdx.x;
-            if (e < d.nao * d.nocc) d.Cf[e] = (float)d.C[e];
+            if (e < d.nao * d.nocc) d.Cf[e / d.nocc * d.ldcf + e % d.nocc] = (float)d.C[e];
             break;
         }
         case BP_SYRK:
-            k_syrk_body<float>(lid, d.X, d.nao, d.naux * d.nocc, d.nao, d.nocc, nullptr, d.kchunk, d.ntl,
+            k_syrk_body<float, SY_SYM, true>(lid, d.X, d.ldx, d.naux * d.nocc, d.nao, d.nocc, nullptr, d.kchunk,
+                                             d.ntl,
                                d.kpart);
             break;
         case BP_KFIN:
@@ -1029,8 +1029,8 @@ __global__ __launch_bounds__(kThreads) void kb_gemm1(const MolDesc* __restrict__
     const int64_t b = xcd_logical(blockIdx.x, pl.nblk);
     const int j = find_mol_k(pl.prefix, pl.n, b);
     const MolDesc& d = mols[pl.ids[j]];
-    k_gemm1_body<float, TS, NI, WM>(b - pl.prefix[j], static_cast<const TS*>(d.B), d.ldB, d.nao, d.Cf,
-                                     d.nocc, d.nocc, d.X, d.nao, d.g1_nib, d.g1_nmb);
+    k_gemm1_body<float, TS, NI, WM, 4>(b - pl.prefix[j], static_cast<const TS*>(d.B), d.ldB, d.nao, d.Cf,
+                                        d.ldcf, d.nocc, d.X, d.ldx, d.g1_nib, d.g1_nmb);
 }
 
 template <int NI, int WM>
@@ -1051,8 +1051,8 @@ __global__ __launch_bounds__(kThreads) void kb_gemm1w(const MolDesc* __restrict_
     const int64_t b = xcd_logical(blockIdx.x, pl.nblk);
     const int j = find_mol_k(pl.prefix, pl.n, b);
     const MolDesc& d = mols[pl.ids[j]];
-    k_gemm1w_body<TS, NJ, WJ>(b - pl.prefix[j], static_cast<const TS*>(d.B), d.ldB, d.nao, d.Cf, d.nocc,
-                              d.nocc, d.X, d.nao, d.g1_nib, d.g1_nmb);
+    k_gemm1w_body<TS, NJ, WJ, 4>(b - pl.prefix[j], static_cast<const TS*>(d.B), d.ldB, d.nao, d.Cf, d.ldcf,
+                                 d.nocc, d.X, d.ldx, d.g1_nib, d.g1_nmb);
 }
 
 template <int NJ, int WJ>
