@@ -167,7 +167,10 @@ def traffic_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_wr
         out = collections.OrderedDict()
         for k in sorted(vals):
             out.setdefault(names[k], []).append(vals[k])
+            first_id.setdefault(names[k], k)
         return out
+
+    first_id = {}  # kernel name -> its first dispatch id (FETCH_SIZE run)
 
     gib = float(1 << 30)
     cf = per_dispatch(copy_fetch_dir, "FETCH_SIZE")
@@ -175,8 +178,10 @@ def traffic_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_wr
     ck = [k for k in cf if "copyBuffer" in k][0]
     f_scale = gib / (float(np.median(cf[ck])) * 1024.0)
     w_scale = gib / (float(np.median(cw[ck])) * 1024.0)
-    fe = per_dispatch(fetch_dir, "FETCH_SIZE")
     wr = per_dispatch(write_dir, "WRITE_SIZE")
+    first_id.clear()
+    fe = per_dispatch(fetch_dir, "FETCH_SIZE")
+    k_fin_first = first_id.get("k_syrk_finish<double>", 1 << 62)
     cfg = __import__("synth").C2
     npair = cfg.nao * (cfg.nao + 1) // 2
     b_bytes = cfg.naux * npair * 8.0
@@ -191,14 +196,15 @@ def traffic_summary(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_wr
         w_kib = float(np.mean(wr[name][:first]))
         byts = f_kib * 1024.0 * f_scale + w_kib * 1024.0 * w_scale
         key = None
-        if name.startswith("k_gemm1<double"):
+        if name.startswith("k_gemm1<double") and first_id[name] < k_fin_first:
+            # the launches of the J/K step's K (the first K finish follows them)
             g1_total += byts
             key = "k_gemm1_f64 launch " + name
         elif name.startswith("j_rho_f64<"):
             key = "j_rho_f64"
         elif name.startswith("j_out_f64<") and name.endswith("false>"):
             key = "j_out_f64"
-        elif name == "k_syrk<double, 0>":
+        elif name.startswith("k_syrk<double, 0"):
             key = "k_syrk_f64"
         mn = mins.get(key)
         rows.append(f"| `{name}` | {f_kib:.4g} | {w_kib:.4g} | {byts:.4g} | "
