@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 CASES = [
-    # nao, naux, nocc, seed, ld_pad  -- several tiles, ragged tails, odd row stride
+    # nao, naux, nocc, seed, ld_pad  -- several tiles, ragged tails, odd row stride;
+    # even and odd nao: the GEMM2 stages X rows with 16-byte loads when they are
+    # 16-byte aligned (even nao in FP64) and one element per load otherwise
     (64, 256, 16, 1, 0),
     (300, 77, 37, 11, 3),
     (129, 33, 1, 12, 0),

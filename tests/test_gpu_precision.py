@@ -61,6 +61,10 @@ def test_quantize_bit_exact(pkg):
         assert np.array_equal(f, oracle.quantize_f32(x))
 
 
+# nao, naux, nocc, seed, ld_pad: rows of X and C^T that are whole 16-byte
+# vectors (nao, nocc multiples of 4: 16-byte staging loads) and that are not
+# (element loads at the row ends), and a padded row stride of B (its
+# 16-byte loads at every alignment)
 CASES = [(64, 256, 16, 1, 0), (300, 77, 37, 31, 0), (129, 40, 9, 32, 3)]
 
 
