@@ -433,8 +433,20 @@ __global__ __launch_bounds__(kThreads) void k_gemm1w(const TS* __restrict__ B, i
                               ioff, iend);
 }
 
+// Waves per SIMD the register allocation is held to (LDS allows them):
+// FP64 (7,1) 3 instead of 2 (nao=1024, nocc=200: 35.5 -> 34.6 ms for the
+// GEMM1 phase); FP32 (13,1) on 16-bit B 4 instead of 3 (nao=2048, nocc=400:
+// 309 -> 299 ms, with a 48-byte spill; on FP32 B the same bound ran slower,
+// 18.95 -> 19.70 ms, so that tile keeps 3).
 template <typename T, typename TS, int NI, int WM>
-__global__ __launch_bounds__(kThreads) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
+constexpr int g1_waves() {
+    return (sizeof(T) == 8 && NI == 7 && WM == 1) ? 3
+           : (sizeof(T) == 4 && sizeof(TS) == 2 && NI == 13 && WM == 1) ? 4
+                                                                          : 1;
+}
+
+template <typename T, typename TS, int NI, int WM>
+__global__ __launch_bounds__(kThreads, (g1_waves<T, TS, NI, WM>())) void k_gemm1(const TS* __restrict__ B, int64_t ldB, int64_t nao,
                                                      const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                                      T* __restrict__ X, int64_t ldx, int64_t nib,
                                                      int64_t nmb, int64_t nblk, int64_t ioff, int64_t iend) {
