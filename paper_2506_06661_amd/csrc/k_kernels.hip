@@ -450,9 +450,9 @@ __global__ __launch_bounds__(kThreads, (g1_waves<T, TS, NI, WM>())) void k_gemm1
                                                      const T* __restrict__ C, int64_t ldc, int64_t ncol,
                                                      T* __restrict__ X, int64_t ldx, int64_t nib,
                                                      int64_t nmb, int64_t nblk, int64_t ioff, int64_t iend) {
-    // FP32: C staged 16 bytes per load (measured faster: 21.5 -> 19.4 ms for
-    // the (13,1) tile at nao=1024, nocc=200); FP64 and the batched kernels
-    // keep one element per load (36.9 against 35.7 ms, and the batch slower)
+    // FP32: C and B staged up to 16 bytes per load (measured faster: 21.5 ->
+    // 19.05 ms for the (13,1) tile at nao=1024, nocc=200); FP64 keeps one
+    // element per load (wide C ran 36.9 against 35.7 ms, wide B no faster)
     k_gemm1_body<T, TS, NI, WM, sizeof(T) == 4 ? 4 : 1>(xcd_logical(blockIdx.x, nblk), B, ldB, nao, C, ldc, ncol, X, ldx, nib,
                                 nmb, ioff, iend);
 }
@@ -784,7 +784,8 @@ struct G1Tile {
 // Tiles 14..16: the FP32 32 x 32 x 2 form, (NI, WM) = (2 NJ, 2 WJ); no FP64
 // launcher (FP64 has no 32 x 32 step).  Not defaults: at nao=1024,
 // naux=4096, nocc=200 (FP32 B) on MI355X they took 24.9 / 29.7 / 28.0 ms
-// against 21.5 ms for (13,1) on 16 x 16 x 4 steps.
+// against 21.5 ms for (13,1) on 16 x 16 x 4 steps (both with one element
+// per staging load; (13,1) takes 19.1-19.3 ms with the wide staging).
 #define G1W(a, b)                                                                              \
     {                                                                                          \
         2 * a, 2 * b, {                                                                        \
@@ -813,8 +814,9 @@ __global__ void to_f32(const double* __restrict__ x, int64_t n, float* __restric
 // that keep two waves per SIMD (FP64 sweep on MI355X, nao=1024, nocc=200:
 // (7,1) 43.8 TFLOP/s, (5,2) 43.5, (13,1) 40.4, (1,2) 32.6).
 // FP32 compute (FP32/BF16/FP16 storage) allows up to 14 accumulator tiles
-// (sweep at nocc=200, FP32 B: (13,1) and (7,2) 79.7 TFLOP/s, (5,2) 76.6,
-// (7,1) 76.0, (5,1) 68.7, (8,2) 72.5, (4,4) 62.5).
+// (sweep at nocc=200, FP32 B, one element per staging load: (13,1) and
+// (7,2) 79.7 TFLOP/s, (5,2) 76.6, (7,1) 76.0, (5,1) 68.7, (8,2) 72.5,
+// (4,4) 62.5).
 int pick_g1_tile(int64_t ncol, bool f32 = false) {
     int best = 0;
     double best_cost = 1e300;
