@@ -1038,8 +1038,14 @@ __global__ __launch_bounds__(kThreads) void kb_kernel(int kind, const MolDesc* _
     }
 }
 
+// Batched GEMM1 tiles with at most 8 accumulator blocks are held to 5 waves
+// per SIMD (their LDS allows 6); larger ones would spill.
+template <int NI, int WM>
+constexpr int kb_g1_waves() { return NI * WM <= 8 ? 5 : 1; }
+
 template <typename TS, int NI, int WM>
-__global__ __launch_bounds__(kThreads) void kb_gemm1(const MolDesc* __restrict__ mols, PhaseList pl) {
+__global__ __launch_bounds__(kThreads, (kb_g1_waves<NI, WM>())) void kb_gemm1(const MolDesc* __restrict__ mols,
+                                                                             PhaseList pl) {
     const int64_t b = xcd_logical(blockIdx.x, pl.nblk);
     const int j = find_mol_k(pl.prefix, pl.n, b);
     const MolDesc& d = mols[pl.ids[j]];
